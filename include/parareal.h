@@ -1,0 +1,172 @@
+/*
+ * parareal.h -- C ABI of an MI355X (gfx950) library for Parareal and
+ * asynchronous Parareal time integration of the heat equation
+ *     du/dt = nu * Laplace(u)  on (0,1)^d, d = 1, 2, 3, u = 0 on the boundary,
+ * following Magoules & Gbikpi-Benissan, "Asynchronous parareal time
+ * discretization for partial differential equations" (arXiv 2110.10762).
+ *
+ * Problem statement (Section 3.1, equation (pde) and the time decomposition
+ * [T_{i-1}, T_i], i = 1..N): the caller gives the PDE data (nu, zero Dirichlet
+ * boundary), the initial value u0, the end time T and the number of slices N,
+ * the choice of fine and coarse propagators, and the stopping threshold eps of
+ * equation (thresh).  The library returns the slice-boundary values
+ * lambda_i ~ u(T_i), i = 0..N.
+ *
+ * Discretisation: n interior points per dimension, h = 1/(n+1), zero ghost
+ * values.  F = m explicit-Euler steps of the (2d+1)-point Laplacian with
+ * m = max(1, ceil(dT/dt_nominal - 1e-9)), dT = T/N, dt = dT/m.  G = one
+ * backward-Euler step of length dT (Thomas in 1D, conjugate gradients in 2D/3D).
+ *
+ * Memory: every double* is DEVICE memory on the handle's device, contiguous
+ * FP64, C order with x fastest ([z][y][x]).  A state has n^d values; an
+ * iterate lambda has (N+1) states, slice 0 first.  For a batch of problems
+ * (pr_create with nproblems > 1) the per-problem arrays are concatenated in
+ * problem order.  The caller owns all pointers it passes; the library owns its
+ * workspace (allocated by pr_create or lazily by the first solve of a kind,
+ * freed by pr_destroy) and never keeps a caller pointer after a call returns.
+ *
+ * Streams: all work is queued on the stream given to pr_create (NULL = the
+ * null stream).  Calls return after their work has completed, because the
+ * stop decisions and statistics are needed on the host.
+ *
+ * Errors: every int-returning call returns PR_OK (0) or a negative PR_E* code
+ * and leaves a message for pr_last_error() (per thread).  No C++ exception
+ * crosses the ABI.  A handle is not thread-safe; calls on one handle must not
+ * overlap.
+ */
+#ifndef PARAREAL_H
+#define PARAREAL_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PR_OK            0
+#define PR_EINVAL       -1   /* bad argument (dimension, size, null pointer...) */
+#define PR_EUNSTABLE    -2   /* explicit Euler unstable: r = nu*dt/h^2 > 1/(2d) */
+#define PR_ENOMEM       -3   /* device allocation failed */
+#define PR_EHIP         -4   /* HIP runtime error (message holds the HIP string) */
+#define PR_ENOTCONV     -5   /* kmax reached before the threshold; outputs written */
+#define PR_ENORESIDENT  -6   /* persistent teams cannot all be resident at once */
+#define PR_ETIMEOUT     -7   /* a bounded device-side wait ran out; outputs invalid */
+
+#define PR_COARSE_AUTO    0  /* Thomas in 1D, CG otherwise */
+#define PR_COARSE_THOMAS  1  /* 1D only */
+#define PR_COARSE_CG      2
+
+typedef struct pr_problem pr_problem;   /* opaque, library-owned */
+
+typedef struct pr_config {
+    int    dim;          /* 1, 2 or 3 */
+    int    n;            /* interior points per dimension, >= 1 */
+    double nu;           /* diffusivity, > 0 */
+    double T;            /* end time, > 0 */
+    int    nslices;      /* N >= 1 (the paper's p) */
+    double dt_nominal;   /* requested fine step, > 0 */
+    int    coarse;       /* PR_COARSE_* */
+    double cg_tol;       /* CG relative residual ||r||_2 <= tol ||b||_2; <= 0 means 1e-12 */
+    int    cg_maxit;     /* <= 0 means 10*n + 100 */
+    double eps;          /* stop when ||lambda^k - lambda^{k-1}||_inf < eps; <= 0: run kmax */
+    int    kmax;         /* iteration cap; <= 0 or > N means N (finite termination) */
+    int    tb_depth;     /* fine steps per HBM pass (temporal block depth); 0 = tuned */
+    int    tile_rows;    /* rows per register strip of the fine kernel; 0 = tuned */
+} pr_config;
+
+/* Derived discretisation of one problem (read-only view). */
+typedef struct pr_info {
+    int    m;            /* fine steps per slice */
+    double dt, dT, h;
+    double r;            /* nu*dt/h^2 */
+    double s;            /* nu*dT/h^2 */
+    long long npts;      /* n^dim */
+    long long offset;    /* index of this problem's lambda_0[0] in a concatenated iterate */
+    int    tb_depth, tile_rows;   /* fine-kernel shape in use */
+} pr_info;
+
+typedef struct pr_stats {
+    /* inputs (optional, caller-owned host arrays) */
+    int    *k_per_slice;     /* [N] local iteration counts k_i (async) or NULL */
+    double *deltas;          /* [deltas_cap] ||lambda^k - lambda^{k-1}||_inf per iteration, or NULL */
+    int     deltas_cap;
+    /* outputs */
+    int    iters;            /* sync: k at stop; async: kappa = max_i k_i; fine: 0 */
+    int    kappa;
+    int    converged;        /* 1 if the threshold (or exactness) was reached */
+    double last_delta;
+    double wall_ms;          /* whole call, device events */
+    double fine_ms;          /* time in fine-propagator kernels (sync) */
+    double coarse_ms;        /* time in coarse sweeps (sync) */
+    double fine_lups;        /* lattice-site updates performed by F */
+    long long cg_iters;      /* total CG iterations */
+    long long g_solves;      /* coarse solves performed */
+    long long g_skipped;     /* coarse solves skipped (unchanged input) */
+} pr_stats;
+
+/* Asynchronous-driver options (Algorithm 2 emulated by persistent teams). */
+#define PR_ASYNC_FREE    0   /* read the newest predecessor; tolerance stop */
+#define PR_ASYNC_EXACT   1   /* run until the finite-termination cascade reaches slice N */
+#define PR_ASYNC_REPLAY  2   /* read the versions a host schedule names (deterministic) */
+
+typedef struct pr_async_opts {
+    int mode;                /* PR_ASYNC_* */
+    int teams;               /* concurrent slice teams; 0 = automatic */
+    int max_local_iters;     /* cap on k_i (<= 0: 4*N + 16) */
+    const int *schedule;     /* REPLAY: host array [N][max_local_iters]: predecessor
+                                version read by slice i's k-th coarse solve (slice 1: 0) */
+    const int *delay_spins;  /* optional host array [N]: extra busy-wait per local iteration
+                                (emulates slow processors / late messages); NULL = none */
+} pr_async_opts;
+
+/* Create a handle for one problem (nproblems == 1) or a batch of independent
+ * problems solved in one persistent launch (nproblems > 1).  device: HIP
+ * device ordinal; stream: hipStream_t or NULL.  Validates every config
+ * (PR_EINVAL, PR_EUNSTABLE) and allocates the synchronous workspace. */
+int  pr_create(const pr_config *cfgs, int nproblems, int device, void *stream,
+               pr_problem **out);
+void pr_destroy(pr_problem *h);
+const char *pr_last_error(void);
+int  pr_get_info(const pr_problem *h, int problem, pr_info *out);
+
+/* Synchronous Parareal, equation (pr), with the slice guards of Algorithm 1
+ * (slices already exact are not recomputed).  u0: [sum npts]; lambda_out:
+ * [sum (N+1)*npts], the final iterate.  stats: NULL or an array of nproblems.
+ * Returns PR_ENOTCONV if some problem hit kmax (< N) first. */
+int  pr_solve_sync (pr_problem *h, const double *u0, double *lambda_out, pr_stats *stats);
+
+/* Asynchronous Parareal, equation (apr) as Algorithm 2: one team of
+ * workgroups per slice (or per group of slices), no grid-wide barrier; each
+ * team publishes its iterate through versioned device slots and reads the
+ * newest (or scheduled) predecessor version.  Single problem only. */
+int  pr_set_async_options(pr_problem *h, const pr_async_opts *opts);
+int  pr_solve_async(pr_problem *h, const double *u0, double *lambda_out, pr_stats *stats);
+
+/* Serial fine integration lambda_i = F(lambda_{i-1}) (Section 3.1), the
+ * fixed point both Parareal variants reach. */
+int  pr_solve_fine (pr_problem *h, const double *u0, double *lambda_out, pr_stats *stats);
+
+/* Adjoint of the fine integration for L = 1/2 ||u(T) - u_target||^2 given
+ * the upstream gradient gT = dL/du(T) [npts] and slice-boundary checkpoints
+ * lambda [(N+1)*npts] (the converged iterate).  Writes dL/du0 [npts] (device)
+ * and dL/dnu (host scalar).  Forward states inside a slice are recomputed
+ * from lambda_{i-1} with sub-checkpoints.  Single problem only. */
+int  pr_grad(pr_problem *h, const double *lambda, const double *gT,
+             double *dLdu0, double *dLdnu);
+
+/* Kernel-level entry points (tests, microbenchmarks); single problem only.
+ * pr_apply_fine: out[c] = steps explicit-Euler steps of in[c], c < count
+ *   (steps <= 0 means m); in and out may not overlap.
+ * pr_apply_coarse: out[c] = G(in[c]) for c < count; cg_iters (host, may be
+ *   NULL) receives the total CG iterations. */
+int  pr_apply_fine  (pr_problem *h, const double *in, double *out, int count, int steps);
+int  pr_apply_coarse(pr_problem *h, const double *in, double *out, int count, long long *cg_iters);
+
+/* Fine-kernel shape control (autotuner and tests): the supported shapes are
+ * enumerated by index; pr_set_fine_shape selects one for a problem. */
+int  pr_fine_shape_count(int dim);
+int  pr_fine_shape_get(int dim, int index, int *tb_depth, int *tile_rows, int *xpts);
+int  pr_set_fine_shape(pr_problem *h, int problem, int tb_depth, int tile_rows);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PARAREAL_H */

@@ -1,0 +1,276 @@
+"""Python binding of libparareal.so (the C ABI in include/parareal.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Device buffers are passed as torch CUDA tensors (float64,
+contiguous) or raw integer device pointers.  The binding refuses to run if
+the compiled library is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libparareal.so")
+
+PR_OK = 0
+PR_EINVAL = -1
+PR_EUNSTABLE = -2
+PR_ENOMEM = -3
+PR_EHIP = -4
+PR_ENOTCONV = -5
+PR_ENORESIDENT = -6
+PR_ETIMEOUT = -7
+
+PR_COARSE_AUTO = 0
+PR_COARSE_THOMAS = 1
+PR_COARSE_CG = 2
+
+PR_ASYNC_FREE = 0
+PR_ASYNC_EXACT = 1
+PR_ASYNC_REPLAY = 2
+
+
+class pr_config(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n", ctypes.c_int), ("nu", ctypes.c_double),
+        ("T", ctypes.c_double), ("nslices", ctypes.c_int), ("dt_nominal", ctypes.c_double),
+        ("coarse", ctypes.c_int), ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
+        ("eps", ctypes.c_double), ("kmax", ctypes.c_int), ("tb_depth", ctypes.c_int),
+        ("tile_rows", ctypes.c_int),
+    ]
+
+
+class pr_info(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int), ("dt", ctypes.c_double), ("dT", ctypes.c_double),
+        ("h", ctypes.c_double), ("r", ctypes.c_double), ("s", ctypes.c_double),
+        ("npts", ctypes.c_longlong), ("offset", ctypes.c_longlong),
+        ("tb_depth", ctypes.c_int), ("tile_rows", ctypes.c_int),
+    ]
+
+
+class pr_stats(ctypes.Structure):
+    _fields_ = [
+        ("k_per_slice", ctypes.POINTER(ctypes.c_int)),
+        ("deltas", ctypes.POINTER(ctypes.c_double)),
+        ("deltas_cap", ctypes.c_int),
+        ("iters", ctypes.c_int), ("kappa", ctypes.c_int), ("converged", ctypes.c_int),
+        ("last_delta", ctypes.c_double), ("wall_ms", ctypes.c_double),
+        ("fine_ms", ctypes.c_double), ("coarse_ms", ctypes.c_double),
+        ("fine_lups", ctypes.c_double), ("cg_iters", ctypes.c_longlong),
+        ("g_solves", ctypes.c_longlong), ("g_skipped", ctypes.c_longlong),
+    ]
+
+
+class pr_async_opts(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int), ("teams", ctypes.c_int), ("max_local_iters", ctypes.c_int),
+        ("schedule", ctypes.POINTER(ctypes.c_int)), ("delay_spins", ctypes.POINTER(ctypes.c_int)),
+    ]
+
+
+EXPORTS = [
+    "pr_create", "pr_destroy", "pr_last_error", "pr_get_info", "pr_solve_sync",
+    "pr_set_async_options", "pr_solve_async", "pr_solve_fine", "pr_grad",
+    "pr_apply_fine", "pr_apply_coarse", "pr_fine_shape_count", "pr_fine_shape_get",
+    "pr_set_fine_shape",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libparareal.so (built by paper_2110_10762_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2110_10762_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.pr_create.argtypes = [ctypes.POINTER(pr_config), ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(P)]
+    lib.pr_destroy.argtypes = [P]
+    lib.pr_destroy.restype = None
+    lib.pr_last_error.restype = ctypes.c_char_p
+    lib.pr_get_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(pr_info)]
+    for name in ("pr_solve_sync", "pr_solve_async", "pr_solve_fine"):
+        getattr(lib, name).argtypes = [P, P, P, ctypes.POINTER(pr_stats)]
+    lib.pr_set_async_options.argtypes = [P, ctypes.POINTER(pr_async_opts)]
+    lib.pr_grad.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_double)]
+    lib.pr_apply_fine.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int]
+    lib.pr_apply_coarse.argtypes = [P, P, P, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
+    lib.pr_fine_shape_count.argtypes = [ctypes.c_int]
+    lib.pr_fine_shape_get.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3
+    lib.pr_set_fine_shape.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+class PRError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _check(rc: int, allow=()):
+    if rc != PR_OK and rc not in allow:
+        raise PRError(rc, load_library().pr_last_error().decode())
+    return rc
+
+
+def _ptr(x) -> int:
+    """Device pointer of a torch tensor (float64, contiguous, on a GPU) or an int."""
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("expected a torch tensor or an integer device pointer")
+    if not x.is_cuda:
+        raise ValueError("buffers must live in GPU memory")
+    if x.dtype != torch.float64 or not x.is_contiguous():
+        raise ValueError("buffers must be contiguous float64")
+    return x.data_ptr()
+
+
+def make_config(dim, n, nu, T, nslices, dt_nominal, coarse=PR_COARSE_AUTO, cg_tol=1e-12,
+                cg_maxit=0, eps=1e-10, kmax=0, tb_depth=0, tile_rows=0) -> pr_config:
+    return pr_config(dim, n, nu, T, nslices, dt_nominal, coarse, cg_tol, cg_maxit, eps, kmax,
+                     tb_depth, tile_rows)
+
+
+def config_of(problem, **over) -> pr_config:
+    """pr_config for a workloads.Problem (keyword overrides allowed)."""
+    kw = dict(dim=problem.dim, n=problem.n, nu=problem.nu, T=problem.T,
+              nslices=problem.nslices, dt_nominal=problem.dt_nominal,
+              cg_tol=problem.cg_tol, eps=problem.eps)
+    kw.update(over)
+    return make_config(**kw)
+
+
+class Stats:
+    """Host-side view of pr_stats with optional per-slice and per-iteration arrays."""
+
+    def __init__(self, nslices: int = 0, deltas_cap: int = 0):
+        self.raw = pr_stats()
+        self._k = (ctypes.c_int * nslices)() if nslices else None
+        self._d = (ctypes.c_double * deltas_cap)() if deltas_cap else None
+        if self._k is not None:
+            self.raw.k_per_slice = ctypes.cast(self._k, ctypes.POINTER(ctypes.c_int))
+        if self._d is not None:
+            self.raw.deltas = ctypes.cast(self._d, ctypes.POINTER(ctypes.c_double))
+            self.raw.deltas_cap = deltas_cap
+
+    @property
+    def k_per_slice(self):
+        return list(self._k) if self._k is not None else None
+
+    @property
+    def deltas(self):
+        if self._d is None:
+            return None
+        return list(self._d)[: max(0, min(self.raw.iters, len(self._d)))]
+
+    def __getattr__(self, name):
+        return getattr(self.raw, name)
+
+    def as_dict(self):
+        d = {f: getattr(self.raw, f) for f, _ in pr_stats._fields_ if f not in ("k_per_slice", "deltas")}
+        if self._k is not None:
+            d["k_per_slice"] = self.k_per_slice
+        if self._d is not None:
+            d["deltas"] = self.deltas
+        return d
+
+
+class Problem:
+    """Owns one library handle (one problem, or a batch when given several configs)."""
+
+    def __init__(self, cfgs, device: int = 0, stream: Optional[int] = None):
+        lib = load_library()
+        if isinstance(cfgs, pr_config):
+            cfgs = [cfgs]
+        arr = (pr_config * len(cfgs))(*cfgs)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib.pr_create(arr, len(cfgs), device, ctypes.c_void_p(stream), ctypes.byref(h)))
+        self.h = h
+        self.lib = lib
+        self.nproblems = len(cfgs)
+        self.cfgs = list(cfgs)
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.pr_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self, problem: int = 0) -> pr_info:
+        out = pr_info()
+        _check(self.lib.pr_get_info(self.h, problem, ctypes.byref(out)))
+        return out
+
+    def _solve(self, fn, u0, lam, stats: Optional[Stats], allow=()):
+        st = stats.raw if stats is not None else None
+        return _check(fn(self.h, _ptr(u0), _ptr(lam), ctypes.byref(st) if st is not None else None), allow)
+
+    def solve_sync(self, u0, lam, stats: Optional[Stats] = None, allow_notconv=False):
+        return self._solve(self.lib.pr_solve_sync, u0, lam, stats, (PR_ENOTCONV,) if allow_notconv else ())
+
+    def solve_async(self, u0, lam, stats: Optional[Stats] = None, allow_notconv=False):
+        return self._solve(self.lib.pr_solve_async, u0, lam, stats, (PR_ENOTCONV,) if allow_notconv else ())
+
+    def solve_fine(self, u0, lam, stats: Optional[Stats] = None):
+        return self._solve(self.lib.pr_solve_fine, u0, lam, stats)
+
+    def set_async_options(self, mode=PR_ASYNC_FREE, teams=0, max_local_iters=0,
+                          schedule: Optional[Sequence[int]] = None,
+                          delay_spins: Optional[Sequence[int]] = None):
+        o = pr_async_opts()
+        o.mode, o.teams, o.max_local_iters = mode, teams, max_local_iters
+        keep = []
+        if schedule is not None:
+            arr = (ctypes.c_int * len(schedule))(*schedule)
+            keep.append(arr)
+            o.schedule = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int))
+        if delay_spins is not None:
+            arr = (ctypes.c_int * len(delay_spins))(*delay_spins)
+            keep.append(arr)
+            o.delay_spins = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int))
+        _check(self.lib.pr_set_async_options(self.h, ctypes.byref(o)))
+
+    def grad(self, lam, gT, dldu0) -> float:
+        out = ctypes.c_double()
+        _check(self.lib.pr_grad(self.h, _ptr(lam), _ptr(gT), _ptr(dldu0), ctypes.byref(out)))
+        return out.value
+
+    def apply_fine(self, x, y, count: int, steps: int = 0):
+        _check(self.lib.pr_apply_fine(self.h, _ptr(x), _ptr(y), count, steps))
+
+    def apply_coarse(self, x, y, count: int) -> int:
+        it = ctypes.c_longlong()
+        _check(self.lib.pr_apply_coarse(self.h, _ptr(x), _ptr(y), count, ctypes.byref(it)))
+        return it.value
+
+    def set_fine_shape(self, tb_depth: int, tile_rows: int, problem: int = 0):
+        _check(self.lib.pr_set_fine_shape(self.h, problem, tb_depth, tile_rows))
+
+
+def fine_shapes(dim: int):
+    lib = load_library()
+    out = []
+    for i in range(lib.pr_fine_shape_count(dim)):
+        d, r, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib.pr_fine_shape_get(dim, i, ctypes.byref(d), ctypes.byref(r), ctypes.byref(x)))
+        out.append((d.value, r.value, x.value))
+    return out

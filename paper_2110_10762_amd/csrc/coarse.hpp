@@ -1,0 +1,275 @@
+// Coarse propagator G: one backward-Euler step of length dT,
+//     (I - nu dT L_h) w = x,
+// the cheap per-slice solver of Section 3.1 (the paper's experiment uses
+// backward Euler as G, Section 5.1).
+//   1D: the tridiagonal system is solved by the Thomas algorithm written as
+//       two first-order affine recurrences and evaluated by one wave with a
+//       log-depth lane scan (the elimination factors are the same for every
+//       slice and iteration and are precomputed once on the host).
+//   2D/3D: textbook conjugate gradients started from x0 = b, stopped at
+//       ||r||_2 <= tol ||b||_2, executed by a team of workgroups with
+//       deterministic team reductions (two team barriers per iteration: the
+//       search-direction update is fused into the matrix-vector product).
+#pragma once
+#include "common.hpp"
+
+namespace pr {
+
+// ------------------------------------------------------------------ 1D Thomas
+// With a = c = -s, b = 1 + 2s and inv_i = 1 / (b - a c'_{i-1}), c'_i = -s inv_i:
+//   forward   d_i = s inv_i d_{i-1} + inv_i x_i        (coefficient 0 at i = 0)
+//   backward  w_i = s inv_i w_{i+1} + d_i             (coefficient 0 at i = n-1)
+// Each lane holds R consecutive points; a lane's points compose to one affine
+// map, and the maps are combined across lanes by a Hillis-Steele scan.
+template <int R>
+__device__ __forceinline__ void thomas_wave(double (&x)[R], const double (&inv)[R], int n, double s) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    double fa[R];
+    double A = 1.0, B = 0.0;
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        const int i = lane * R + e;
+        fa[e] = (i == 0 || i >= n) ? 0.0 : s * inv[e];
+        const double fb = x[e] * inv[e];
+        B = __builtin_fma(fa[e], B, fb);
+        A = fa[e] * A;
+        x[e] = fb;
+    }
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const double Ap = __shfl_up(A, o, WAVE);
+        const double Bp = __shfl_up(B, o, WAVE);
+        if (lane >= o) {
+            B = __builtin_fma(A, Bp, B);
+            A = A * Ap;
+        }
+    }
+    double d = __shfl_up(B, 1, WAVE);
+    if (lane == 0) d = 0.0;
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        d = __builtin_fma(fa[e], d, x[e]);
+        x[e] = d;
+    }
+    // backward recurrence, scanned from the top lane down
+    double bc[R];
+    double C = 1.0, E = 0.0;
+#pragma unroll
+    for (int e = R - 1; e >= 0; --e) {
+        const int i = lane * R + e;
+        bc[e] = (i >= n - 1) ? 0.0 : s * inv[e];
+        E = __builtin_fma(bc[e], E, x[e]);
+        C = bc[e] * C;
+    }
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const double Cp = __shfl_down(C, o, WAVE);
+        const double Ep = __shfl_down(E, o, WAVE);
+        if (lane + o < WAVE) {
+            E = __builtin_fma(C, Ep, E);
+            C = C * Cp;
+        }
+    }
+    double w = __shfl_down(E, 1, WAVE);
+    if (lane == WAVE - 1) w = 0.0;
+#pragma unroll
+    for (int e = R - 1; e >= 0; --e) {
+        w = __builtin_fma(bc[e], w, x[e]);
+        x[e] = w;
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void load_inv(const double *tab, double (&inv)[R]) {
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int e = 0; e < R; ++e) inv[e] = tab[lane * R + e];   // table padded to 64*R
+}
+
+template <int R>
+__global__ __launch_bounds__(64) void k_thomas(const double *__restrict__ src, double *__restrict__ dst,
+                                               long long stride, int n, double s, const double *inv_tab,
+                                               int count) {
+    const int st = blockIdx.x;
+    if (st >= count) return;
+    const int lane = threadIdx.x;
+    double x[R], inv[R];
+    load_inv<R>(inv_tab, inv);
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        const int p = lane * R + e;
+        x[e] = p < n ? src[st * stride + p] : 0.0;
+    }
+    thomas_wave<R>(x, inv, n, s);
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        const int p = lane * R + e;
+        if (p < n) dst[st * stride + p] = x[e];
+    }
+}
+
+// ------------------------------------------------------------------ geometry
+// A state is split into chunks of 64 consecutive x values of one grid row;
+// a team's workgroups own contiguous chunk ranges, its waves stride over them.
+struct Geom {
+    int dim, n;
+    long long npts;
+    int cpr;            // chunks per row
+    long long nchunks;  // rows * cpr
+};
+
+__host__ __device__ inline Geom make_geom(int dim, int n) {
+    Geom g;
+    g.dim = dim;
+    g.n = n;
+    long long rows = 1;
+    for (int d = 1; d < dim; ++d) rows *= n;
+    g.npts = rows * n;
+    g.cpr = (n + WAVE - 1) / WAVE;
+    g.nchunks = rows * g.cpr;
+    return g;
+}
+
+struct ChunkRange {
+    long long begin, end;
+};
+
+__device__ __forceinline__ ChunkRange team_chunks(const Geom &g, int rank, int size) {
+    const long long per = (g.nchunks + size - 1) / size;
+    ChunkRange cr;
+    cr.begin = per * rank;
+    cr.end = min(g.nchunks, cr.begin + per);
+    return cr;
+}
+
+struct Point {
+    long long idx;
+    int x, y, z;
+    bool valid;
+};
+
+__device__ __forceinline__ Point chunk_point(const Geom &g, long long c) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const long long row = c / g.cpr;
+    const int cx = (int)(c - row * g.cpr);
+    Point p;
+    p.x = cx * WAVE + lane;
+    if (g.dim == 3) {
+        p.y = (int)(row % g.n);
+        p.z = (int)(row / g.n);
+    } else {
+        p.y = (int)row;
+        p.z = 0;
+    }
+    p.valid = p.x < g.n;
+    p.idx = row * g.n + p.x;
+    return p;
+}
+
+// Sum of the 2d neighbour values of f (zero outside the domain), in the
+// order ((y-pair [+ z-pair]) + x-pair).
+template <typename Fn>
+__device__ __forceinline__ double neighbour_sum(const Geom &g, const Point &p, Fn f) {
+    const long long n = g.n;
+    const double xl = p.x > 0 ? f(p.idx - 1) : 0.0;
+    const double xr = p.x + 1 < g.n ? f(p.idx + 1) : 0.0;
+    double s2 = 0.0;
+    if (g.dim >= 2) {
+        const double yu = p.y > 0 ? f(p.idx - n) : 0.0;
+        const double yd = p.y + 1 < g.n ? f(p.idx + n) : 0.0;
+        s2 = yu + yd;
+        if (g.dim == 3) {
+            const double zf = p.z > 0 ? f(p.idx - n * n) : 0.0;
+            const double zb = p.z + 1 < g.n ? f(p.idx + n * n) : 0.0;
+            s2 = s2 + (zf + zb);
+        }
+    }
+    return s2 + (xl + xr);
+}
+
+// (I - s h^2 L_h) y at a point, given y there and the neighbour sum.
+__device__ __forceinline__ double be_point(double yc, double nsum, double twod, double s) {
+    const double lap = __builtin_fma(-twod, yc, nsum);
+    return __builtin_fma(-s, lap, yc);
+}
+
+// ------------------------------------------------------------------ CG
+struct CGWork {
+    double *r, *p0, *p1, *q;   // [npts] each
+    double *red;               // [2 * team size] reduction slots
+};
+
+// Solves (I - s h^2 L_h) x = b by CG with the team.  Returns the iteration
+// count, or -1 if the launch was aborted.  x and b must not alias.
+__device__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
+                       const double *__restrict__ b, double *__restrict__ x, const CGWork &wk) {
+    __shared__ double lds[WAVES_PER_BLOCK];
+    const double twod = 2.0 * g.dim;
+    const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
+    const int w = wave_id();
+    int par = 0;   // alternates the reduction slot arrays (write-after-read safety)
+
+    // r = b - A b, x = b
+    double rr_p = 0.0, bb_p = 0.0;
+    for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+        const Point p = chunk_point(g, c);
+        if (!p.valid) continue;
+        const double bc = b[p.idx];
+        const double ns = neighbour_sum(g, p, [&](long long j) { return b[j]; });
+        const double rv = bc - be_point(bc, ns, twod, s);
+        x[p.idx] = bc;
+        wk.r[p.idx] = rv;
+        rr_p = __builtin_fma(rv, rv, rr_p);
+        bb_p = __builtin_fma(bc, bc, bb_p);
+    }
+    double rr, bb;
+    if (!team_reduce<false>(tm, bb_p, wk.red + par * tm.size, bb, lds)) return -1;
+    par ^= 1;
+    if (!team_reduce<false>(tm, rr_p, wk.red + par * tm.size, rr, lds)) return -1;
+    par ^= 1;
+    const double thresh = tol * tol * bb;
+
+    const double *pold = wk.r;   // first direction: p = r (beta = 0)
+    double beta = 0.0;
+    double *pcur = wk.p0;
+    int it = 0;
+    while (it < maxit && rr > thresh) {
+        // phase A: p = r + beta p_old (also at neighbours), q = A p, <p, q>
+        double pq_p = 0.0;
+        for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+            const Point p = chunk_point(g, c);
+            if (!p.valid) continue;
+            auto pn = [&](long long j) { return __builtin_fma(beta, pold[j], wk.r[j]); };
+            const double pc = pn(p.idx);
+            const double qv = be_point(pc, neighbour_sum(g, p, pn), twod, s);
+            pcur[p.idx] = pc;
+            wk.q[p.idx] = qv;
+            pq_p = __builtin_fma(pc, qv, pq_p);
+        }
+        double pq;
+        if (!team_reduce<false>(tm, pq_p, wk.red + par * tm.size, pq, lds)) return -1;
+        par ^= 1;
+        const double alpha = rr / pq;
+        // phase B: x += alpha p, r -= alpha q, <r, r>
+        double rn_p = 0.0;
+        for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+            const Point p = chunk_point(g, c);
+            if (!p.valid) continue;
+            x[p.idx] = __builtin_fma(alpha, pcur[p.idx], x[p.idx]);
+            const double rv = __builtin_fma(-alpha, wk.q[p.idx], wk.r[p.idx]);
+            wk.r[p.idx] = rv;
+            rn_p = __builtin_fma(rv, rv, rn_p);
+        }
+        double rn;
+        if (!team_reduce<false>(tm, rn_p, wk.red + par * tm.size, rn, lds)) return -1;
+        par ^= 1;
+        beta = rn / rr;
+        rr = rn;
+        pold = pcur;
+        pcur = (pcur == wk.p0) ? wk.p1 : wk.p0;
+        ++it;
+    }
+    return it;
+}
+
+}  // namespace pr

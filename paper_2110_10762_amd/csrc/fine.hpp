@@ -1,0 +1,266 @@
+// Fine propagator F: explicit-Euler steps of the (2d+1)-point Laplacian with
+// zero Dirichlet ghosts (the accurate per-slice solver of Section 3.1).
+//
+// Every slice is independent, so one launch advances a batch of states.
+// All kernels are wave-granular and barrier-free:
+//   1D: one wave per state, the whole state in registers (R points per lane),
+//       halos by DPP lane shifts, all steps in one launch.
+//   2D: register strips.  A wave owns 64*XP columns by R+2D rows (XP points
+//       per lane in x, one register per row), loads them once from HBM, does
+//       up to D steps (temporal blocking: the valid region shrinks by one row
+//       and column per step), and writes back the inner R x (64*XP - 2D)
+//       block.  y-neighbours are other registers of the same lane, x-neighbours
+//       come from DPP lane shifts.
+//   3D: one step per pass; a wave owns an (x, y) strip of 64*XP by R+2 and
+//       marches along z with three planes in registers.
+// Out-of-domain halo values are loaded from the odd reflection of the state
+// (see reflect()), which keeps the ghost values exactly zero without masks.
+#pragma once
+#include "common.hpp"
+
+namespace pr {
+
+// ------------------------------------------------------------------ 1D
+template <int R>
+__device__ __forceinline__ void fine1d_regs(double (&c)[R], const double (&rl)[R], int steps) {
+    for (int t = 0; t < steps; ++t) {
+        const double left_edge = from_lower_lane(c[R - 1]);
+        const double right_edge = from_upper_lane(c[0]);
+        double prev = left_edge;
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+            const double cur = c[e];
+            const double nxt = (e + 1 < R) ? c[e + 1] : right_edge;
+            const double tt = __builtin_fma(-2.0, cur, prev + nxt);
+            c[e] = __builtin_fma(rl[e], tt, cur);
+            prev = cur;
+        }
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void load1d(const double *src, int n, double r, double (&c)[R], double (&rl)[R]) {
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        const int p = lane * R + e;
+        c[e] = p < n ? src[p] : 0.0;
+        rl[e] = p < n ? r : 0.0;   // padding points stay exactly zero
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void store1d(double *dst, int n, const double (&c)[R]) {
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        const int p = lane * R + e;
+        if (p < n) dst[p] = c[e];
+    }
+}
+
+// grid: one wave (block of 64) per state
+template <int R>
+__global__ __launch_bounds__(64) void k_fine1d(const double *__restrict__ src, double *__restrict__ dst,
+                                               long long sstride, long long dstride, int n, double r,
+                                               int steps, int count) {
+    const int st = blockIdx.x;
+    if (st >= count) return;
+    double c[R], rl[R];
+    load1d<R>(src + (long long)st * sstride, n, r, c, rl);
+    fine1d_regs<R>(c, rl, steps);
+    store1d<R>(dst + (long long)st * dstride, n, c);
+}
+
+// ------------------------------------------------------------------ 2D
+template <int XP, int R, int D>
+struct Shape2D {
+    static constexpr int H = R + 2 * D;          // rows held per lane
+    static constexpr int W = WAVE * XP - 2 * D;  // useful columns per strip
+};
+
+// One strip pass: load, `steps` (<= D) explicit-Euler steps, store.
+template <int XP, int R, int D>
+__device__ __forceinline__ void fine2d_strip(const double *__restrict__ src, double *__restrict__ dst,
+                                             int n, double r, int steps, int sx, int sy) {
+    constexpr int H = Shape2D<XP, R, D>::H;
+    constexpr int W = Shape2D<XP, R, D>::W;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int x0 = sx * W - D;
+    const int y0 = sy * R - D;
+    double c[XP][H];
+    int xi[XP];
+    double xs[XP];
+#pragma unroll
+    for (int e = 0; e < XP; ++e) xi[e] = reflect(x0 + lane * XP + e, n, xs[e]);
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        double ys;
+        const int yi = reflect(y0 + j, n, ys);
+        const double *row = src + (long long)yi * n;
+#pragma unroll
+        for (int e = 0; e < XP; ++e) c[e][j] = (ys * xs[e]) * row[xi[e]];
+    }
+    for (int t = 0; t < steps; ++t) {
+        double prev[XP];
+#pragma unroll
+        for (int e = 0; e < XP; ++e) prev[e] = c[e][0];
+#pragma unroll
+        for (int j = 1; j < H - 1; ++j) {
+            double cur[XP], lr[XP];
+#pragma unroll
+            for (int e = 0; e < XP; ++e) cur[e] = c[e][j];
+            if constexpr (XP == 1) {
+                lr[0] = from_lower_lane(cur[0]) + from_upper_lane(cur[0]);
+            } else {
+                lr[0] = from_lower_lane(cur[XP - 1]) + cur[1];
+#pragma unroll
+                for (int e = 1; e < XP - 1; ++e) lr[e] = cur[e - 1] + cur[e + 1];
+                lr[XP - 1] = cur[XP - 2] + from_upper_lane(cur[0]);
+            }
+#pragma unroll
+            for (int e = 0; e < XP; ++e) {
+                c[e][j] = euler_update(cur[e], lr[e], prev[e] + c[e][j + 1], 4.0, r);
+                prev[e] = cur[e];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = D; j < D + R; ++j) {
+        const int y = y0 + j;
+        if (y < n) {
+            double *row = dst + (long long)y * n;
+#pragma unroll
+            for (int e = 0; e < XP; ++e) {
+                const int lx = lane * XP + e;
+                const int x = x0 + lx;
+                if (lx >= D && lx < D + W && x < n) row[x] = c[e][j];
+            }
+        }
+    }
+}
+
+// Workgroups are re-indexed so that each XCD (dispatch round-robins blocks
+// over the 8 XCDs) receives a contiguous range of strips: vertically
+// adjacent strips then share their halo rows through that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblk) {
+    const int per = (nblk + 7) / 8;
+    return (b % 8) * per + b / 8;
+}
+
+template <int XP, int R, int D>
+__global__ __launch_bounds__(BLOCK) void k_fine2d(const double *__restrict__ src, double *__restrict__ dst,
+                                                  long long sstride, long long dstride, int n, double r,
+                                                  int steps, int nsx, int nsy, int count, int nblk) {
+    const int L = xcd_remap(blockIdx.x, nblk);
+    if (L >= nblk) return;
+    const long long wv = (long long)L * WAVES_PER_BLOCK + wave_id();
+    const long long per_state = (long long)nsx * nsy;
+    if (wv >= per_state * count) return;
+    const int st = (int)(wv / per_state);
+    const int rem = (int)(wv - (long long)st * per_state);
+    const int sy = rem % nsy;          // vertical neighbours are consecutive waves
+    const int sx = rem / nsy;
+    fine2d_strip<XP, R, D>(src + st * sstride, dst + st * dstride, n, r, steps, sx, sy);
+}
+
+// ------------------------------------------------------------------ 3D
+template <int XP, int R>
+__device__ __forceinline__ void load_plane3d(const double *__restrict__ src, int n, int z, int y0,
+                                             const int (&xi)[XP], const double (&xs)[XP],
+                                             double (&p)[XP][R + 2]) {
+    double zs;
+    const int zi = reflect(z, n, zs);
+    const double *pl = src + (long long)zi * n * n;
+#pragma unroll
+    for (int j = 0; j < R + 2; ++j) {
+        double ys;
+        const int yi = reflect(y0 + j, n, ys);
+        const double *row = pl + (long long)yi * n;
+#pragma unroll
+        for (int e = 0; e < XP; ++e) p[e][j] = (zs * ys * xs[e]) * row[xi[e]];
+    }
+}
+
+template <int XP, int R>
+__device__ __forceinline__ void step_plane3d(double *__restrict__ dst, int n, int z, int y0, int x0,
+                                             double r, const double (&pm)[XP][R + 2],
+                                             const double (&pc)[XP][R + 2], const double (&pp)[XP][R + 2]) {
+    constexpr int W = WAVE * XP - 2;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (z >= n) return;
+    double *pl = dst + (long long)z * n * n;
+#pragma unroll
+    for (int j = 1; j <= R; ++j) {
+        double lr[XP];
+        if constexpr (XP == 1) {
+            lr[0] = from_lower_lane(pc[0][j]) + from_upper_lane(pc[0][j]);
+        } else {
+            lr[0] = from_lower_lane(pc[XP - 1][j]) + pc[1][j];
+#pragma unroll
+            for (int e = 1; e < XP - 1; ++e) lr[e] = pc[e - 1][j] + pc[e + 1][j];
+            lr[XP - 1] = pc[XP - 2][j] + from_upper_lane(pc[0][j]);
+        }
+        const int y = y0 + j;
+#pragma unroll
+        for (int e = 0; e < XP; ++e) {
+            const double s2 = (pc[e][j - 1] + pc[e][j + 1]) + (pm[e][j] + pp[e][j]);
+            const double v = euler_update(pc[e][j], lr[e], s2, 6.0, r);
+            const int lx = lane * XP + e;
+            const int x = x0 + lx;
+            if (y < n && lx >= 1 && lx < 1 + W && x < n) pl[(long long)y * n + x] = v;
+        }
+    }
+}
+
+// One explicit-Euler step of a 3D state, strip (sx, sy) over planes [z0, z1).
+template <int XP, int R>
+__device__ __forceinline__ void fine3d_strip(const double *__restrict__ src, double *__restrict__ dst,
+                                             int n, double r, int sx, int sy, int z0, int z1) {
+    constexpr int W = WAVE * XP - 2;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int x0 = sx * W - 1;
+    const int y0 = sy * R - 1;
+    int xi[XP];
+    double xs[XP];
+#pragma unroll
+    for (int e = 0; e < XP; ++e) xi[e] = reflect(x0 + lane * XP + e, n, xs[e]);
+    double a[XP][R + 2], b[XP][R + 2], c[XP][R + 2];
+    load_plane3d<XP, R>(src, n, z0 - 1, y0, xi, xs, a);
+    load_plane3d<XP, R>(src, n, z0, y0, xi, xs, b);
+    int z = z0;
+    // unrolled by three so that the plane roles rotate without register moves
+    while (z < z1) {
+        load_plane3d<XP, R>(src, n, z + 1, y0, xi, xs, c);
+        step_plane3d<XP, R>(dst, n, z, y0, x0, r, a, b, c);
+        if (++z >= z1) break;
+        load_plane3d<XP, R>(src, n, z + 1, y0, xi, xs, a);
+        step_plane3d<XP, R>(dst, n, z, y0, x0, r, b, c, a);
+        if (++z >= z1) break;
+        load_plane3d<XP, R>(src, n, z + 1, y0, xi, xs, b);
+        step_plane3d<XP, R>(dst, n, z, y0, x0, r, c, a, b);
+        ++z;
+    }
+}
+
+template <int XP, int R>
+__global__ __launch_bounds__(BLOCK) void k_fine3d(const double *__restrict__ src, double *__restrict__ dst,
+                                                  long long sstride, long long dstride, int n, double r,
+                                                  int nsx, int nsy, int nsz, int zc, int count, int nblk) {
+    const int L = xcd_remap(blockIdx.x, nblk);
+    if (L >= nblk) return;
+    const long long wv = (long long)L * WAVES_PER_BLOCK + wave_id();
+    const long long per_state = (long long)nsx * nsy * nsz;
+    if (wv >= per_state * count) return;
+    const int st = (int)(wv / per_state);
+    int rem = (int)(wv - (long long)st * per_state);
+    const int sy = rem % nsy;
+    rem /= nsy;
+    const int sz = rem % nsz;
+    const int sx = rem / nsz;
+    const int z0 = sz * zc;
+    const int z1 = min(n, z0 + zc);
+    fine3d_strip<XP, R>(src + st * sstride, dst + st * dstride, n, r, sx, sy, z0, z1);
+}
+
+}  // namespace pr

@@ -1,0 +1,164 @@
+// Synchronous Parareal sweeps (equation (pr); Algorithm 1's guards).
+//
+// One iteration k of the synchronous driver is
+//   (1) v_i = F(lambda_{i-1}^{k-1}) for every slice i >= k, all independent
+//       (fine kernels, one launch over the batch of slices), then
+//   (2) the sequential coarse sweep i = k..N:
+//         w_new = G(lambda_{i-1}^k)          (skipped for i = k: its input is
+//                                             exact and unchanged, so w_new = w_old)
+//         lambda_i^k = v_i + (w_new - w_old)  (this evaluation order leaves
+//                                             exactly v_i when w_new == w_old)
+//         delta = max(delta, |lambda_i^k - lambda_i^{k-1}|)
+// The sweep of (2) runs in one launch: a single wave in 1D, the whole GPU as
+// one team in 2D/3D (the team barrier separates consecutive slices).  The
+// initial coarse sweep lambda_i^0 = G(lambda_{i-1}^0), w_i = lambda_i^0 uses
+// the same kernels in "init" mode.
+#pragma once
+#include "coarse.hpp"
+
+namespace pr {
+
+struct SweepArgs {
+    double *lam;        // [(N+1) * npts], updated in place
+    const double *v;    // [(N+1) * npts], v[i] = F(lambda_{i-1})
+    double *w;          // [(N+1) * npts], w[i] = G of slice i's last coarse input
+    double *wn;         // [npts] scratch for the new coarse value
+    long long npts;
+    int i0, i1;         // slices to sweep, inclusive
+    int kguard;         // slice whose coarse input is known unchanged (-1: none)
+    int init;           // 1: initial coarse sweep
+    double *delta;      // max-norm change (bit pattern max, zeroed by the host)
+    unsigned long long *cg_iters;   // accumulated CG iterations (2D/3D)
+    // 1D
+    int n;
+    double s;
+    const double *inv_tab;
+    // 2D/3D
+    Geom g;
+    double cg_tol;
+    int cg_maxit;
+    CGWork wk;
+    unsigned *ctr;
+    Control *ctl;
+};
+
+template <int R>
+__global__ __launch_bounds__(64) void k_sweep_1d(SweepArgs a) {
+    const int lane = threadIdx.x;
+    const int n = a.n;
+    double inv[R];
+    load_inv<R>(a.inv_tab, inv);
+    double x[R];   // input of the next coarse solve: lambda_{i-1} (new)
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        const int p = lane * R + e;
+        x[e] = p < n ? a.lam[(a.i0 - 1) * a.npts + p] : 0.0;
+    }
+    double dmax = 0.0;
+    for (int i = a.i0; i <= a.i1; ++i) {
+        double *li = a.lam + i * a.npts;
+        double *wi = a.w + i * a.npts;
+        const double *vi = a.v + i * a.npts;
+        double wnew[R];
+        const bool skip = (i == a.kguard);
+#pragma unroll
+        for (int e = 0; e < R; ++e) wnew[e] = x[e];
+        if (!skip) thomas_wave<R>(wnew, inv, n, a.s);
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+            const int p = lane * R + e;
+            double lnew = 0.0;
+            if (p < n) {
+                if (a.init) {
+                    lnew = wnew[e];
+                    wi[p] = lnew;
+                } else {
+                    const double wold = wi[p];
+                    const double wv = skip ? wold : wnew[e];
+                    lnew = vi[p] + (wv - wold);
+                    dmax = fmax(dmax, fabs(lnew - li[p]));
+                    wi[p] = wv;
+                }
+                li[p] = lnew;
+            }
+            x[e] = lnew;
+        }
+    }
+    dmax = wave_max(dmax);
+    if (lane == 0 && !a.init) atomic_max_nonneg(a.delta, dmax);
+}
+
+// Cooperative launch: the whole grid is one team.
+__global__ __launch_bounds__(BLOCK) void k_sweep_cg(SweepArgs a) {
+    Team tm{a.ctr, a.ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
+    const ChunkRange cr = team_chunks(a.g, tm.rank, tm.size);
+    const int w = wave_id();
+    double dmax = 0.0;
+    unsigned long long its = 0;
+    for (int i = a.i0; i <= a.i1; ++i) {
+        const double *b = a.lam + (long long)(i - 1) * a.npts;
+        double *li = a.lam + (long long)i * a.npts;
+        double *wi = a.w + (long long)i * a.npts;
+        const double *vi = a.v + (long long)i * a.npts;
+        const bool skip = (i == a.kguard);
+        if (!skip) {
+            const int it = cg_team(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, a.wn, a.wk);
+            if (it < 0) return;
+            its += (unsigned long long)it;
+        }
+        for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+            const Point p = chunk_point(a.g, c);
+            if (!p.valid) continue;
+            if (a.init) {
+                const double wv = a.wn[p.idx];
+                li[p.idx] = wv;
+                wi[p.idx] = wv;
+            } else {
+                const double wold = wi[p.idx];
+                const double wv = skip ? wold : a.wn[p.idx];
+                const double lnew = vi[p.idx] + (wv - wold);
+                dmax = fmax(dmax, fabs(lnew - li[p.idx]));
+                li[p.idx] = lnew;
+                wi[p.idx] = wv;
+            }
+        }
+        if (!team_sync(tm)) return;
+    }
+    __shared__ double lds[WAVES_PER_BLOCK];
+    dmax = block_reduce<true>(dmax, lds);
+    if (threadIdx.x == 0) {
+        if (!a.init) atomic_max_nonneg(a.delta, dmax);
+        if (tm.rank == 0)
+            __hip_atomic_fetch_add(a.cg_iters, its, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Batch of independent coarse solves (tests and the apply entry point):
+// state c of the batch is solved by the whole grid, one after the other.
+__global__ __launch_bounds__(BLOCK) void k_coarse_cg_batch(const double *src, double *dst, long long npts,
+                                                           int count, Geom g, double s, double tol,
+                                                           int maxit, CGWork wk, unsigned *ctr,
+                                                           Control *ctl, unsigned long long *cg_iters) {
+    Team tm{ctr, ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
+    unsigned long long its = 0;
+    for (int c = 0; c < count; ++c) {
+        const int it = cg_team(tm, g, s, tol, maxit, src + c * npts, dst + c * npts, wk);
+        if (it < 0) return;
+        its += (unsigned long long)it;
+        if (!team_sync(tm)) return;
+    }
+    if (threadIdx.x == 0 && tm.rank == 0)
+        __hip_atomic_fetch_add(cg_iters, its, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_zero_words(unsigned *p, int nwords) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nwords) p[i] = 0u;
+}
+
+__global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst, long long n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace pr
