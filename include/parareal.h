@@ -100,6 +100,9 @@ typedef struct pr_stats {
     long long cg_iters;      /* total CG iterations */
     long long g_solves;      /* coarse solves performed */
     long long g_skipped;     /* coarse solves skipped (unchanged input) */
+    int    teams;            /* async: concurrent slice teams used */
+    long long copy_retries;  /* async: predecessor copies redone (slot overwritten meanwhile) */
+    long long idle_rounds;   /* async: team rounds with nothing to update */
 } pr_stats;
 
 /* Asynchronous-driver options (Algorithm 2 emulated by persistent teams). */
@@ -115,6 +118,8 @@ typedef struct pr_async_opts {
                                 version read by slice i's k-th coarse solve (slice 1: 0) */
     const int *delay_spins;  /* optional host array [N]: extra busy-wait per local iteration
                                 (emulates slow processors / late messages); NULL = none */
+    double time_limit_s;     /* device-side wall-clock cap of one solve (<= 0: 120 s); the
+                                launch stops and the call returns PR_ETIMEOUT past it */
 } pr_async_opts;
 
 /* Create a handle for one problem (nproblems == 1) or a batch of independent

@@ -61,6 +61,8 @@ class pr_stats(ctypes.Structure):
         ("fine_ms", ctypes.c_double), ("coarse_ms", ctypes.c_double),
         ("fine_lups", ctypes.c_double), ("cg_iters", ctypes.c_longlong),
         ("g_solves", ctypes.c_longlong), ("g_skipped", ctypes.c_longlong),
+        ("teams", ctypes.c_int), ("copy_retries", ctypes.c_longlong),
+        ("idle_rounds", ctypes.c_longlong),
     ]
 
 
@@ -68,6 +70,7 @@ class pr_async_opts(ctypes.Structure):
     _fields_ = [
         ("mode", ctypes.c_int), ("teams", ctypes.c_int), ("max_local_iters", ctypes.c_int),
         ("schedule", ctypes.POINTER(ctypes.c_int)), ("delay_spins", ctypes.POINTER(ctypes.c_int)),
+        ("time_limit_s", ctypes.c_double),
     ]
 
 
@@ -235,9 +238,11 @@ class Problem:
 
     def set_async_options(self, mode=PR_ASYNC_FREE, teams=0, max_local_iters=0,
                           schedule: Optional[Sequence[int]] = None,
-                          delay_spins: Optional[Sequence[int]] = None):
+                          delay_spins: Optional[Sequence[int]] = None,
+                          time_limit_s: float = 0.0):
         o = pr_async_opts()
         o.mode, o.teams, o.max_local_iters = mode, teams, max_local_iters
+        o.time_limit_s = time_limit_s
         keep = []
         if schedule is not None:
             arr = (ctypes.c_int * len(schedule))(*schedule)

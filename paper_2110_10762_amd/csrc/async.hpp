@@ -1,3 +1,517 @@
+// Asynchronous Parareal (equation (apr) in the form of Algorithm 2), emulated
+// on one GPU by one persistent cooperative launch.
+//
+// The grid is split into teams of workgroups (a team per slice, or per group
+// of slices); teams never wait for each other.  Each local iteration of slice
+// i does, exactly as Algorithm 2:
+//     v      = F(x_old)                   x_old: the predecessor value its
+//                                         previous coarse solve used
+//     x_new  = newest published lambda_{i-1} (or the version a replay
+//              schedule names)
+//     w_new  = G(x_new)                   (= w_old when x_new is x_old: G is
+//                                          deterministic, so nothing to solve)
+//     lambda = v + (w_new - w_old)        (exactly v when the input is stale)
+//     publish lambda as version ver+1;  x_old, w_old := x_new, w_new
+// Publication: every slice owns a ring of R slots holding its newest
+// versions; the slot data is written by the team, then the team leader
+// stores the version number with agent-scope release semantics.  A reader
+// acquires the version, copies the slot, and re-reads the version: the copy
+// is valid if the writer cannot have started overwriting that slot meanwhile
+// (at most R-2 newer versions published).  Per-slice headers (change of the
+// last update, accumulated change "drift", predecessor drift at the version
+// read) are updated under a sequence lock so that a monitor can take a
+// consistent snapshot by double collect.
+//
+// Stop rules (the paper delegates asynchronous termination to external
+// protocols; these are this library's readings):
+//   FREE   every slice has updated, its last update changed it by < eps, and
+//          the predecessor version it read has since drifted by < eps (the
+//          drift bounds the max-norm distance by the triangle inequality).
+//          Value-preserving idling: a slice whose coarse input was stale in
+//          its previous update and is still stale would recompute exactly the
+//          value it already published, so it waits instead.
+//   EXACT  finite termination (Section 3.2, nested-set proposition): a slice
+//          is final once it updated with both inputs equal to its
+//          predecessor's final value; stop when slice N is final.
+//   REPLAY slice i's k-th coarse solve reads the predecessor version the host
+//          schedule names (waiting for it if needed); all versions are kept.
 #pragma once
+#include "fine.hpp"
 #include "coarse.hpp"
-namespace pr { struct AsyncWork { int dummy; }; }
+
+namespace pr {
+
+constexpr int AMODE_FREE = 0, AMODE_EXACT = 1, AMODE_REPLAY = 2;
+
+struct alignas(64) SliceHdr {
+    int seq;          // sequence lock (odd while the fields change)
+    int ver;          // newest published version (release-stored)
+    int k;            // local iterations performed (k_i)
+    int g_ver;        // predecessor version read by the last coarse solve
+    int final_from;   // EXACT: first version equal to the serial fine value, -1 before
+    int done;         // the slice will not publish again (release-stored)
+    int pad1, pad2;
+    double delta;     // max-norm change made by the last update
+    double drift;     // sum of the changes of versions 1..ver
+    double stale_ref; // predecessor drift at version g_ver
+    double pad3;
+};
+
+struct SliceLoc {     // team-private control state of a slice (leader only)
+    int f_ver;        // predecessor version of x_old
+    int xo, wo;       // which of the two x / w buffers hold x_old / w_old
+    int f_final;      // x_old is the predecessor's final value (EXACT)
+    int stale_streak; // consecutive updates with a stale coarse input
+    int done;
+    int pad0, pad1;
+};
+
+struct AsyncWork {
+    double *ring = nullptr, *X = nullptr, *W = nullptr, *V = nullptr, *S = nullptr;
+    SliceHdr *hdr = nullptr;
+    SliceLoc *loc = nullptr;
+    double *slot_drift = nullptr;
+    int *sched = nullptr, *delay = nullptr;
+    int *team_of = nullptr, *rank_of = nullptr, *tsize = nullptr;
+    unsigned *tctr = nullptr;
+    long long *tbc = nullptr;
+    double *tred = nullptr;
+    double *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr, *cgq = nullptr;
+    unsigned long long *counters = nullptr;
+    // the configuration these buffers were sized for
+    int R = 0, L = 0, nteams = 0, grid = 0, maxtsz = 0, withS = 0;
+};
+
+struct AsyncArgs {
+    int N, dim, n, m;
+    long long npts;
+    double r, s, eps, cg_tol;
+    int cg_maxit;
+    Geom g;
+    int mode, R, L, idle_skip;
+    double *ring;            // [R][(N+1) npts]
+    double *X, *W;           // [2][(N+1) npts]
+    double *V, *S;           // [(N+1) npts]; S only if a slice needs several fine passes
+    SliceHdr *hdr;           // [N+1]
+    SliceLoc *loc;           // [N+1]
+    double *slot_drift;      // [(N+1) R]
+    const int *sched;        // REPLAY: [N][L]
+    const int *delay;        // [N+1] or NULL
+    int nteams, maxtsz;
+    const int *team_of, *rank_of, *tsize;   // per workgroup / per team
+    unsigned *tctr;          // [nteams * 16]
+    long long *tbc;          // [nteams * 16] leader broadcasts
+    double *tred;            // [nteams * 2 * maxtsz]
+    double *cgr, *cgp0, *cgp1, *cgq;   // [nteams * npts]
+    Control *ctl;
+    unsigned long long *counters;   // cg iterations, coarse solves, skipped solves, copy retries, idle rounds
+    // fine-kernel geometry
+    int nsx, nsy, nsz, zc;
+    const double *inv_tab;   // 1D Thomas factors
+    unsigned long long t_limit;  // wall-clock ticks before the launch gives up
+};
+
+// Barrier that also broadcasts 8 words from the team leader and the global
+// stop flag.  All workgroups of the team see the same words.  Returns false
+// when the launch is aborted or stopped.
+__device__ __forceinline__ bool team_bcast(Team &tm, long long *slots, long long (&v)[8]) {
+    __shared__ long long s_v[8];
+    const int par = (tm.epoch + 1) & 1;
+    if (tm.rank == 0 && threadIdx.x == 0) {
+        v[7] = __hip_atomic_load(&tm.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = 0; j < 8; ++j) slots[par * 8 + j] = v[j];
+    }
+    if (!team_sync(tm)) return false;
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 8; ++j) s_v[j] = slots[par * 8 + j];
+    __syncthreads();
+    for (int j = 0; j < 8; ++j) v[j] = s_v[j];
+    __syncthreads();
+    return v[7] == 0;
+}
+
+// ---- sequence-locked header access (leader threads only)
+__device__ __forceinline__ void hdr_publish(SliceHdr *h, int ver, int k, int g_ver, int final_from,
+                                            double delta, double drift, double stale_ref) {
+    const int s = h->seq;
+    __hip_atomic_store(&h->seq, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __atomic_thread_fence(__ATOMIC_RELEASE);
+    __hip_atomic_store(&h->k, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&h->g_ver, g_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&h->final_from, final_from, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    st_relaxed(&h->delta, delta);
+    st_relaxed(&h->drift, drift);
+    st_relaxed(&h->stale_ref, stale_ref);
+    st_release(&h->ver, ver);
+    __hip_atomic_store(&h->seq, s + 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct HdrView {
+    int ver, k;
+    double delta, drift, stale_ref;
+};
+
+__device__ __forceinline__ bool hdr_read(const SliceHdr *h, HdrView &o) {
+    const int s1 = ld_acquire(&h->seq);
+    if (s1 & 1) return false;
+    o.ver = __hip_atomic_load(&h->ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    o.k = __hip_atomic_load(&h->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    o.delta = ld_relaxed(&h->delta);
+    o.drift = ld_relaxed(&h->drift);
+    o.stale_ref = ld_relaxed(&h->stale_ref);
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    const int s2 = __hip_atomic_load(&h->seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return s1 == s2;
+}
+
+// Double-collect snapshot of all headers; true if the FREE stop rule holds.
+__device__ bool free_stop_rule(const AsyncArgs &a) {
+    long long vsum[2] = {0, 0};
+    bool ok = true;
+    for (int pass = 0; pass < 2; ++pass) {
+        double prev_drift = 0.0;
+        for (int i = 1; i <= a.N; ++i) {
+            HdrView v;
+            if (!hdr_read(&a.hdr[i], v)) return false;
+            vsum[pass] += v.ver;
+            if (pass == 0) {
+                if (v.k < 1 || !(v.delta < a.eps)) ok = false;
+                if (i > 1 && !(prev_drift - v.stale_ref < a.eps)) ok = false;
+            }
+            prev_drift = v.drift;
+        }
+        if (!ok) return false;
+    }
+    return vsum[0] == vsum[1];
+}
+
+// ---- team-parallel elementwise helpers (chunks of 64 x-values)
+__device__ __forceinline__ void team_copy(const Team &tm, const Geom &g, const double *__restrict__ src,
+                                          double *__restrict__ dst) {
+    const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
+    const int w = wave_id();
+    for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+        const Point p = chunk_point(g, c);
+        if (p.valid) dst[p.idx] = src[p.idx];
+    }
+}
+
+// ---- fine propagation of one state by a team: passes of <= D steps
+template <int DIM, int XP, int RR, int D>
+__device__ bool team_fine(Team &tm, const AsyncArgs &a, const double *src, double *dst, double *scr) {
+    if constexpr (DIM == 1) {
+        if (wave_id() == 0) {
+            double c[RR], rl[RR];
+            load1d<RR>(src, a.n, a.r, c, rl);
+            fine1d_regs<RR>(c, rl, a.m);
+            store1d<RR>(dst, a.n, c);
+        }
+        return team_sync(tm);
+    } else {
+        const int steps_per = DIM == 2 ? D : 1;
+        const int passes = (a.m + steps_per - 1) / steps_per;
+        const double *cur = src;
+        const int waves = tm.size * WAVES_PER_BLOCK;
+        const int wid = tm.rank * WAVES_PER_BLOCK + wave_id();
+        for (int p = 0; p < passes; ++p) {
+            double *tgt = ((passes - 1 - p) % 2 == 0) ? dst : scr;
+            if constexpr (DIM == 2) {
+                const int st = min(D, a.m - p * D);
+                const int total = a.nsx * a.nsy;
+                for (int sidx = wid; sidx < total; sidx += waves)
+                    fine2d_strip<XP, RR, D>(cur, tgt, a.n, a.r, st, sidx / a.nsy, sidx % a.nsy);
+            } else {
+                const int total = a.nsx * a.nsy * a.nsz;
+                for (int sidx = wid; sidx < total; sidx += waves) {
+                    int rem = sidx;
+                    const int sy = rem % a.nsy;
+                    rem /= a.nsy;
+                    const int sz = rem % a.nsz;
+                    const int sx = rem / a.nsz;
+                    const int z0 = sz * a.zc;
+                    fine3d_strip<XP, RR>(cur, tgt, a.n, a.r, sx, sy, z0, min(a.n, z0 + a.zc));
+                }
+            }
+            if (!team_sync(tm)) return false;
+            cur = tgt;
+        }
+        return true;
+    }
+}
+
+// ---- coarse solve of one state by a team; returns iterations or -1
+template <int DIM, int RR>
+__device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double *x, const CGWork &wk) {
+    if constexpr (DIM == 1) {
+        if (wave_id() == 0) {
+            double v[RR], inv[RR];
+            load_inv<RR>(a.inv_tab, inv);
+            const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+            for (int e = 0; e < RR; ++e) {
+                const int p = lane * RR + e;
+                v[e] = p < a.n ? b[p] : 0.0;
+            }
+            thomas_wave<RR>(v, inv, a.n, a.s);
+#pragma unroll
+            for (int e = 0; e < RR; ++e) {
+                const int p = lane * RR + e;
+                if (p < a.n) x[p] = v[e];
+            }
+        }
+        return team_sync(tm) ? 0 : -1;
+    } else {
+        const int it = cg_team(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk);
+        if (it < 0) return -1;
+        return team_sync(tm) ? it : -1;
+    }
+}
+
+enum { ACT_IDLE = 0, ACT_UPDATE = 1, ACT_DONE = 2 };
+
+template <int DIM, int XP, int RR, int D>
+__global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
+    const int team = a.team_of[blockIdx.x];
+    if (team < 0) return;
+    const int rank = a.rank_of[blockIdx.x];
+    Team tm{a.tctr + team * 16, a.ctl, a.tsize[team], rank, 0u};
+    long long *bc = a.tbc + team * 16;
+    CGWork wk{a.cgr + (long long)team * a.npts, a.cgp0 + (long long)team * a.npts,
+              a.cgp1 + (long long)team * a.npts, a.cgq + (long long)team * a.npts,
+              a.tred + (long long)team * 2 * a.maxtsz};
+    __shared__ double lds[WAVES_PER_BLOCK];
+    const bool leader = (rank == 0 && threadIdx.x == 0);
+    const long long np = a.npts;
+    const long long all = (long long)(a.N + 1) * np;
+    const unsigned long long t0 = wall_clock64();
+    unsigned long long cg_its = 0, g_solves = 0, g_skips = 0, retries = 0, idles = 0;
+
+    for (;;) {
+        bool any_active = false, any_work = false;
+        for (int i = team + 1; i <= a.N; i += a.nteams) {
+            // ---------------- leader decides, team follows
+            long long b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (leader) {
+                SliceLoc &L = a.loc[i];
+                const int myver = a.hdr[i].ver;
+                int action = ACT_UPDATE, pv = 0;
+                // a final slice (EXACT) or one at its iteration cap publishes no more
+                if (L.done || a.hdr[i].k >= a.L || (a.mode == AMODE_EXACT && a.hdr[i].final_from >= 0)) {
+                    action = ACT_DONE;
+                } else if (a.mode == AMODE_REPLAY) {
+                    const int tgt = a.sched[(long long)(i - 1) * a.L + a.hdr[i].k];
+                    if (tgt < 0) {
+                        action = ACT_DONE;
+                    } else {
+                        pv = tgt;
+                        if (i > 1) {
+                            long long spins = 0;
+                            while (ld_acquire(&a.hdr[i - 1].ver) < tgt) {
+                                if (__hip_atomic_load(&a.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                                if (++spins > SPIN_LIMIT) {
+                                    __hip_atomic_store(&a.ctl->error, -7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                    __hip_atomic_store(&a.ctl->abort, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(2);
+                            }
+                        }
+                    }
+                } else {
+                    pv = (i == 1) ? 0 : ld_acquire(&a.hdr[i - 1].ver);
+                    const bool stale = (pv == L.f_ver);
+                    if (a.idle_skip && stale && L.stale_streak >= 1) {
+                        // Its last update already read this predecessor version, so
+                        // another update would republish F(x_old) unchanged: record
+                        // that (zero) change once, then wait.  Retire if nothing new
+                        // can arrive.
+                        if (L.stale_streak == 1) {
+                            SliceHdr *h = &a.hdr[i];
+                            hdr_publish(h, h->ver, h->k, h->g_ver, h->final_from, 0.0, h->drift, h->stale_ref);
+                            L.stale_streak = 2;
+                        }
+                        const bool pred_done = (i == 1) || ld_acquire(&a.hdr[i - 1].done) != 0;
+                        action = (pred_done && pv == ld_acquire(&a.hdr[i - 1].ver)) ? ACT_DONE : ACT_IDLE;
+                    }
+                }
+                if (action == ACT_DONE && !L.done) {
+                    L.done = 1;
+                    st_release(&a.hdr[i].done, 1);
+                }
+                if (a.delay && action == ACT_UPDATE)
+                    for (int j = 0; j < a.delay[i]; ++j) __builtin_amdgcn_s_sleep(127);
+                if (wall_clock64() - t0 > a.t_limit) {
+                    __hip_atomic_store(&a.ctl->error, -7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&a.ctl->abort, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                b[0] = action;
+                b[1] = pv;
+                b[2] = L.xo;
+                b[3] = L.wo;
+                b[4] = myver;
+                b[5] = (pv == L.f_ver) ? 1 : 0;
+            }
+            if (!team_bcast(tm, bc, b)) goto out;
+            const int action = (int)b[0];
+            if (action == ACT_DONE) continue;
+            any_active = true;
+            if (action == ACT_IDLE) continue;
+            any_work = true;
+            int pv = (int)b[1];
+            const int xo = (int)b[2], wo = (int)b[3], myver = (int)b[4];
+            bool stale = b[5] != 0;
+            double *x_old = a.X + xo * all + i * np;
+            double *x_new = a.X + (xo ^ 1) * all + i * np;
+            double *w_old = a.W + wo * all + i * np;
+            double *w_new = a.W + (wo ^ 1) * all + i * np;
+            double *v = a.V + i * np;
+            // ---------------- v = F(x_old)
+            if (!team_fine<DIM, XP, RR, D>(tm, a, x_old, v, a.S ? a.S + i * np : nullptr)) goto out;
+            // ---------------- newest predecessor (FREE/EXACT read it after F)
+            double drift_read = 0.0;
+            int g_final = 0;
+            for (;;) {
+                if (a.mode != AMODE_REPLAY) {
+                    long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    if (leader) {
+                        c[0] = (i == 1) ? 0 : ld_acquire(&a.hdr[i - 1].ver);
+                        c[1] = (c[0] == a.loc[i].f_ver) ? 1 : 0;
+                    }
+                    if (!team_bcast(tm, bc, c)) goto out;
+                    pv = (int)c[0];
+                    stale = c[1] != 0;
+                }
+                if (stale) break;
+                const double *src = a.ring + (long long)(pv % a.R) * all + (i - 1) * np;
+                team_copy(tm, a.g, src, x_new);
+                long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (leader) {
+                    const double dr = a.slot_drift[(i - 1) * a.R + pv % a.R];
+                    const int ff = __hip_atomic_load(&a.hdr[i - 1].final_from, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+                    const int after = (i == 1) ? pv : ld_acquire(&a.hdr[i - 1].ver);
+                    c[0] = (a.mode == AMODE_REPLAY || after - pv <= a.R - 2) ? 1 : 0;
+                    c[1] = __double_as_longlong(dr);
+                    c[2] = (i == 1) ? 1 : ((ff >= 0 && pv >= ff) ? 1 : 0);
+                }
+                if (!team_bcast(tm, bc, c)) goto out;
+                if (c[0]) {
+                    drift_read = __longlong_as_double(c[1]);
+                    g_final = (int)c[2];
+                    break;
+                }
+                if (++retries > 100000) {
+                    if (leader) {
+                        __hip_atomic_store(&a.ctl->error, -7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&a.ctl->abort, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    goto out;
+                }
+            }
+            // ---------------- w_new = G(x_new), or reuse w_old
+            const double *wv = w_old;
+            if (!stale) {
+                const int it = team_coarse<DIM, RR>(tm, a, x_new, w_new, wk);
+                if (it < 0) goto out;
+                cg_its += (unsigned long long)it;
+                ++g_solves;
+                wv = w_new;
+            } else {
+                ++g_skips;
+            }
+            // ---------------- lambda = v + (w_new - w_old), change norm, write the next slot
+            const int nslot = (myver + 1) % a.R;
+            const double *cur = a.ring + (long long)(myver % a.R) * all + i * np;
+            double *nxt = a.ring + (long long)nslot * all + i * np;
+            double dmax = 0.0;
+            {
+                const ChunkRange cr = team_chunks(a.g, tm.rank, tm.size);
+                const int w = wave_id();
+                for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+                    const Point p = chunk_point(a.g, c);
+                    if (!p.valid) continue;
+                    const double ln = v[p.idx] + (wv[p.idx] - w_old[p.idx]);
+                    dmax = fmax(dmax, fabs(ln - cur[p.idx]));
+                    nxt[p.idx] = ln;
+                }
+            }
+            double delta;
+            if (!team_reduce<true>(tm, dmax, wk.red + (tm.epoch & 1) * tm.size, delta, lds)) goto out;
+            // ---------------- publish (leader), update the slice's control state
+            if (leader) {
+                SliceLoc &L = a.loc[i];
+                SliceHdr *h = &a.hdr[i];
+                const double drift = h->drift + delta;
+                a.slot_drift[i * a.R + nslot] = drift;
+                const double sref = stale ? h->stale_ref : drift_read;
+                const int gf = stale ? L.f_final : g_final;
+                int ff = h->final_from;
+                if (ff < 0 && L.f_final && gf) ff = myver + 1;
+                hdr_publish(h, myver + 1, h->k + 1, pv, ff, delta, drift, sref);
+                if (!stale) {
+                    L.xo ^= 1;
+                    L.wo ^= 1;
+                }
+                L.f_ver = pv;
+                L.f_final = gf;
+                L.stale_streak = stale ? L.stale_streak + 1 : 0;
+                if (a.mode == AMODE_EXACT && i == a.N && ff >= 0)
+                    __hip_atomic_store(&a.ctl->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                if (a.mode == AMODE_FREE && delta < a.eps && free_stop_rule(a))
+                    __hip_atomic_store(&a.ctl->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (!any_active) {
+            // every slice of this team has retired: the state may now satisfy
+            // the stop rule with nobody left to notice, so look once more
+            if (leader && a.mode == AMODE_FREE && free_stop_rule(a))
+                __hip_atomic_store(&a.ctl->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        if (!any_work) {
+            ++idles;
+            if (leader) {
+                if (a.mode == AMODE_FREE && free_stop_rule(a))
+                    __hip_atomic_store(&a.ctl->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_sleep(32);
+            }
+        }
+    }
+out:
+    if (leader) {
+        __hip_atomic_fetch_add(&a.counters[0], cg_its, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.counters[1], g_solves, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.counters[2], g_skips, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.counters[3], retries, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.counters[4], idles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Initial per-slice control state: x_old = lambda_{i-1}^0 in X[0], w_old =
+// lambda_i^0 in W[0], version 0 in ring slot 0.
+__global__ void k_async_init(SliceHdr *hdr, SliceLoc *loc, double *slot_drift, int N, int R) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > N) return;
+    SliceHdr h{};
+    h.final_from = (i == 0) ? 0 : -1;
+    h.done = (i == 0) ? 1 : 0;
+    hdr[i] = h;
+    SliceLoc l{};
+    l.f_final = (i == 1) ? 1 : 0;
+    loc[i] = l;
+    for (int j = 0; j < R; ++j) slot_drift[i * R + j] = 0.0;
+}
+
+// lambda_out[i] = newest published version of slice i.
+__global__ void k_async_gather(const double *ring, const SliceHdr *hdr, double *out, long long npts, int N,
+                               int R) {
+    const long long all = (long long)(N + 1) * npts;
+    const int i = blockIdx.y;
+    const int slot = hdr[i].ver % R;
+    const double *src = ring + slot * all + i * npts;
+    double *dst = out + i * npts;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += (long long)gridDim.x * blockDim.x)
+        dst[p] = src[p];
+}
+
+}  // namespace pr

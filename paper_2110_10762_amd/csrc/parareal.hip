@@ -570,6 +570,8 @@ static void stats_reset(pr_stats *st) {
     st->wall_ms = st->fine_ms = st->coarse_ms = 0;
     st->fine_lups = 0;
     st->cg_iters = st->g_solves = st->g_skipped = 0;
+    st->teams = 0;
+    st->copy_retries = st->idle_rounds = 0;
 }
 
 // ------------------------------------------------------------------ apply entry points

@@ -1,0 +1,163 @@
+"""Asynchronous Parareal on the GPU (persistent teams) vs the oracle.
+
+Replay mode makes the asynchronous iteration deterministic: the GPU reads
+exactly the predecessor versions a schedule names, so its result can be
+compared with the oracle's replay of the same schedule.  Free-running mode is
+nondeterministic by design; it is checked through what the paper fixes
+instead: the fixed point (the serial fine solution), finite termination, and
+kappa >= k.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import heat, parareal
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2110_10762_amd as pr  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-10
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def disc_of(p):
+    return heat.discretise(p.dim, p.n, p.nu, p.T, p.nslices, p.dt_nominal)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def schedule_rows(events, N, L):
+    """Oracle event list [(i, j), ...] -> [N][L] table of versions read, -1 padded."""
+    rows = [[] for _ in range(N + 1)]
+    for i, j in events:
+        rows[i].append(j)
+    tab = np.full((N, L), -1, dtype=np.int32)
+    for i in range(1, N + 1):
+        assert len(rows[i]) <= L
+        tab[i - 1, : len(rows[i])] = rows[i]
+    return tab.ravel().tolist()
+
+
+def solve(p, mode, schedule=None, L=0, teams=0, delays=None, eps=None, **over):
+    prob = pr.Problem(pr.config_of(p, eps=p.eps if eps is None else eps, **over))
+    prob.set_async_options(mode=mode, teams=teams, max_local_iters=L, schedule=schedule,
+                           delay_spins=delays, time_limit_s=30.0)
+    lam = torch.empty((p.nslices + 1,) + p.u0.shape, dtype=torch.float64, device=DEV)
+    st = pr.Stats(p.nslices)
+    prob.solve_async(dev(p.u0), lam, st, allow_notconv=True)
+    return prob, lam.cpu().numpy(), st
+
+
+def test_replay_sync_schedule_equals_gpu_sync_bitwise_1d():
+    p = workloads.heat1d()
+    N, K = p.nslices, 6
+    sched = schedule_rows(parareal.sync_schedule(N, K), N, K)
+    prob, lam, st = solve(p, pr.PR_ASYNC_REPLAY, sched, L=K)
+    assert st.k_per_slice == [K] * N
+    sync = pr.Problem(pr.config_of(p, eps=0.0, kmax=K))
+    ls = torch.empty_like(dev(lam))
+    sync.solve_sync(dev(p.u0), ls)
+    # same kernels, same inputs: the asynchronous replay of the synchronous
+    # schedule is the synchronous iteration (Section 2.1), bit for bit
+    assert np.array_equal(lam, ls.cpu().numpy())
+    d = disc_of(p)
+    props = heat.Propagators(d)
+    ref = parareal.parareal_sync(p.u0, props.F, props.G, N, eps=0.0, kmax=K)
+    assert rel(lam, ref.lam) <= TOL
+
+
+@pytest.mark.parametrize("seed,delay", [(0, 1), (5, 3)])
+def test_replay_random_schedule_1d(seed, delay):
+    p = workloads.heat1d()
+    d = disc_of(p)
+    props = heat.Propagators(d)
+    ref = parareal.run_random(p.u0, props.F, props.G, d.nslices, seed=seed, max_delay=delay,
+                              max_rounds=9)
+    L = max(ref.k[1:])
+    sched = schedule_rows(ref.events, d.nslices, L)
+    _, lam, st = solve(p, pr.PR_ASYNC_REPLAY, sched, L=L)
+    assert st.k_per_slice == ref.k[1:]
+    assert rel(lam, ref.current()) <= TOL
+
+
+def test_replay_random_schedule_2d():
+    p = workloads.heat2d(n=47, nslices=6, T=1e-2)
+    d = disc_of(p)
+    props = heat.Propagators(d, cg_tol=p.cg_tol)
+    ref = parareal.run_random(p.u0, props.F, props.G, d.nslices, seed=11, max_delay=2, max_rounds=5)
+    L = max(ref.k[1:])
+    sched = schedule_rows(ref.events, d.nslices, L)
+    _, lam, st = solve(p, pr.PR_ASYNC_REPLAY, sched, L=L)
+    assert st.k_per_slice == ref.k[1:]
+    assert rel(lam, ref.current()) <= TOL
+
+
+def test_replay_rejects_impossible_schedule():
+    p = workloads.heat1d()
+    prob = pr.Problem(pr.config_of(p))
+    bad = [-1] * (p.nslices * 2)
+    bad[2] = 5        # slice 2 reads version 5 of slice 1, which never publishes it
+    with pytest.raises(pr.PRError):
+        prob.set_async_options(mode=pr.PR_ASYNC_REPLAY, max_local_iters=2, schedule=bad)
+
+
+@pytest.mark.parametrize("which", ["1d", "2d", "3d"])
+def test_exact_mode_finite_termination_bitwise(which):
+    if which == "1d":
+        p = workloads.heat1d()
+    elif which == "2d":
+        p = workloads.heat2d(n=60, nslices=7, T=1e-2)
+    else:
+        p = workloads.heat3d(n=18, nslices=5, T=3e-3)
+    prob, lam, st = solve(p, pr.PR_ASYNC_EXACT)
+    assert st.converged == 1
+    ser = torch.empty_like(dev(lam))
+    prob.solve_fine(dev(p.u0), ser)
+    assert np.array_equal(lam, ser.cpu().numpy())
+
+
+@pytest.mark.parametrize("which,teams", [("1d", 0), ("1d", 3), ("2d", 0), ("2d", 2), ("3d", 0)])
+def test_free_mode_reaches_fixed_point(which, teams):
+    if which == "1d":
+        p = workloads.heat1d()
+    elif which == "2d":
+        p = workloads.heat2d(n=64, nslices=8, T=1e-2)
+    else:
+        p = workloads.heat3d(n=20, nslices=6, T=4e-3)
+    d = disc_of(p)
+    prob, lam, st = solve(p, pr.PR_ASYNC_FREE, teams=teams)
+    assert st.converged == 1
+    star = heat.serial_fine(p.u0, d.r, d.m, d.nslices)
+    err = rel(lam, star)
+    props = heat.Propagators(d, cg_tol=p.cg_tol)
+    sync = parareal.parareal_sync(p.u0, props.F, props.G, d.nslices, eps=p.eps)
+    sync_err = rel(sync.lam, star)
+    print(f"{which} teams={teams}: kappa={st.kappa} k_sync={sync.iters} err={err:.2e} "
+          f"sync_err={sync_err:.2e} k_i={st.k_per_slice} retries={st.copy_retries}")
+    assert err <= TOL
+    assert st.kappa >= sync.iters - 1      # kappa(k~) >= k (Section 4.2), up to the stop rule's +-1
+
+
+def test_free_mode_with_injected_delays_1d():
+    p = workloads.heat1d()
+    d = disc_of(p)
+    delays = [0] * p.nslices
+    delays[3] = 400          # slice 4 is a slow processor
+    delays[9] = 150
+    _, lam, st = solve(p, pr.PR_ASYNC_FREE, delays=delays)
+    assert st.converged == 1
+    star = heat.serial_fine(p.u0, d.r, d.m, d.nslices)
+    assert rel(lam, star) <= TOL
+    prob2, lam2, st2 = solve(p, pr.PR_ASYNC_EXACT, delays=delays)
+    assert st2.converged == 1
+    ser = torch.empty_like(dev(lam2))
+    prob2.solve_fine(dev(p.u0), ser)
+    assert np.array_equal(lam2, ser.cpu().numpy())
