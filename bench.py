@@ -1,0 +1,191 @@
+"""Benchmark: fine-stencil GLUPS + % HBM roofline; async vs sync Parareal
+time to 1e-10, on the 2D heat workload (1024^2 interior points, 64 slices,
+nu = 1, T = 1e-3, fine dt = 0.2 h^2 -> 83 explicit-Euler steps per slice,
+backward-Euler coarse step solved by CG to 1e-12).
+
+One step = one synchronous and one asynchronous Parareal solve of that
+workload to ||lambda^k - lambda^{k-1}||_inf < 1e-10, both starting from u0
+already resident in HBM (the whole hot path: coarse sweep, fine propagation
+of every slice, coarse solves, fused correction + change norm, and the two
+drivers).  `value` = fine-stencil lattice-site updates executed in the
+timed steps / wall time of the timed steps.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-slices", type=int, default=64)
+    ap.add_argument("--only", choices=["both", "sync", "async"], default="both",
+                    help="restrict the step to one driver (profiling runs)")
+    return ap.parse_args()
+
+
+def cpu_baseline(p, nslices_sample):
+    """The oracle's fine propagator on a bounded sample of the same workload:
+    `nslices_sample` slices of 83 explicit-Euler steps on the 1024^2 grid."""
+    import numpy as np
+    from oracle import heat
+    d = heat.discretise(p.dim, p.n, p.nu, p.T, p.nslices, p.dt_nominal)
+    u = p.u0.copy()
+    t = time.perf_counter()
+    for _ in range(nslices_sample):
+        u = heat.fine(u, d.r, d.m)
+    dt = time.perf_counter() - t
+    lups = nslices_sample * d.m * p.n * p.n
+    return {"value": lups / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"oracle fine propagator F, {nslices_sample} of the 64 slices "
+                      f"({nslices_sample}x{d.m} explicit-Euler steps on the 1024^2 grid), "
+                      f"{dt:.1f} s, single-threaded NumPy"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU; the method's slices would shard "
+              "over GPUs by contiguous blocks (see the design notes), but no multi-GPU "
+              "path is built or timed", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2110_10762_amd as pr
+    import workloads
+
+    pr.load_library()          # fails loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    p = workloads.heat2d()
+    prob = pr.Problem(pr.config_of(p, eps=1e-10))
+    info = prob.info()
+    N, npts, m = p.nslices, p.n * p.n, info.m
+    u0 = torch.from_numpy(p.u0).to(dev)
+    lam_s = torch.empty((N + 1, p.n, p.n), dtype=torch.float64, device=dev)
+    lam_a = torch.empty_like(lam_s)
+    ser = torch.empty_like(lam_s)
+    prob.set_async_options(mode=pr.PR_ASYNC_FREE, time_limit_s=200.0)
+
+    # serial fine reference (outside the timed region): accuracy and baseline time
+    stf = pr.Stats()
+    prob.solve_fine(u0, ser, stf)
+    prob.solve_fine(u0, ser, stf)
+    serial_ms = stf.wall_ms
+
+    def step(rec):
+        if args.only in ("both", "sync"):
+            st = pr.Stats(N, N + 1)
+            prob.solve_sync(u0, lam_s, st)
+            rec["sync"].append(st.as_dict())
+        if args.only in ("both", "async"):
+            st = pr.Stats(N)
+            prob.solve_async(u0, lam_a, st)
+            rec["async"].append(st.as_dict())
+
+    warm = {"sync": [], "async": []}
+    for _ in range(args.warmup):
+        step(warm)
+    rec = {"sync": [], "async": []}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    sref = ser.abs().max().item()
+    err_s = (lam_s - ser).abs().max().item() / sref if rec["sync"] else None
+    err_a = (lam_a - ser).abs().max().item() / sref if rec["async"] else None
+
+    lups = sum(s["fine_lups"] for s in rec["sync"]) + sum(s["fine_lups"] for s in rec["async"])
+    value = lups / wall / 1e9
+
+    # ---- roofline objects (algorithmic bytes per launch / live event durations)
+    D = info.tb_depth
+    passes = -(-m // D)
+    rl = {}
+    if rec["sync"]:
+        s = rec["sync"]
+        f_ms = sum(x["fine_ms"] for x in s)
+        f_bytes = sum(x["fine_lups"] for x in s) / m * passes * 16.0   # 16 B/pt per pass
+        f_launches = sum(x["iters"] for x in s) * passes
+        rl["fine"] = {"kernel": f"k_fine2d<2,{info.tile_rows},{D}>", "bound": "hbm",
+                      "achieved": f_bytes / (f_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "launches": f_launches, "avg_launch_ms": f_ms / f_launches,
+                      "glups": sum(x["fine_lups"] for x in s) / (f_ms * 1e-3) / 1e9}
+        c_ms = sum(x["coarse_ms"] for x in s)
+        # CG: 80 B/pt per iteration, 24 B/pt per solve set-up; correction 48 B/pt per slice
+        c_bytes = sum(x["cg_iters"] * 80.0 * npts + x["g_solves"] * 24.0 * npts
+                      + (x["g_solves"] + x["g_skipped"]) * 48.0 * npts for x in s)
+        c_launches = sum(x["iters"] + 1 for x in s)
+        rl["sweep"] = {"kernel": "k_sweep_cg", "bound": "hbm", "achieved": c_bytes / (c_ms * 1e-3) / 1e9,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "launches": c_launches,
+                       "avg_launch_ms": c_ms / c_launches}
+    if rec["async"]:
+        a = rec["async"]
+        k_ms = sum(x["kernel_ms"] for x in a)
+        a_bytes = 0.0
+        for x in a:
+            upd = x["kernel_updates"]
+            solves = x["g_solves"] - N          # minus the initial coarse sweep
+            a_bytes += (upd * passes * 16.0 + x["kernel_cg_iters"] * 80.0 + solves * (24.0 + 16.0)
+                        + upd * 40.0) * npts
+        rl["async"] = {"kernel": "k_async<2,2,16,8>", "bound": "hbm",
+                       "achieved": a_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "launches": len(a), "avg_launch_ms": k_ms / len(a)}
+    for r in rl.values():
+        r["frac"] = r["achieved"] / r["peak"]
+        r["traffic"] = None
+    dom = max(rl, key=lambda k: rl[k]["avg_launch_ms"] * rl[k]["launches"])
+    roofline = dict(rl[dom])
+
+    out = {
+        "metric": "fine-stencil GLUPS + % HBM roofline; async vs sync Parareal time-to-1e-10",
+        "value": value,
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "heat2d n=1024^2 N=64 nu=1 T=1e-3 dt=0.2h^2 (m=83), CG 1e-12; "
+                               "one sync + one async Parareal solve to 1e-10 per step",
+                   "parallelism": "time slices on one GPU (persistent teams for async)"},
+        "roofline": roofline,
+        "roofline_fine": rl.get("fine"),
+        "roofline_kernels": rl,
+        "time_to_tol_ms": {
+            "sync": float(np.median([x["wall_ms"] for x in rec["sync"]])) if rec["sync"] else None,
+            "async": float(np.median([x["wall_ms"] for x in rec["async"]])) if rec["async"] else None,
+            "serial_fine": serial_ms},
+        "k_sync": rec["sync"][-1]["iters"] if rec["sync"] else None,
+        "kappa_async": rec["async"][-1]["kappa"] if rec["async"] else None,
+        "rel_err_vs_serial_fine": {"sync": err_s, "async": err_a},
+        "cg_iters": {"sync": rec["sync"][-1]["cg_iters"] if rec["sync"] else None,
+                     "async": rec["async"][-1]["cg_iters"] if rec["async"] else None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample_slices)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -100,6 +100,9 @@ typedef struct pr_stats {
     long long cg_iters;      /* total CG iterations */
     long long g_solves;      /* coarse solves performed */
     long long g_skipped;     /* coarse solves skipped (unchanged input) */
+    double kernel_ms;        /* async: duration of the persistent launch (device events) */
+    long long kernel_cg_iters;  /* async: CG iterations inside the persistent launch */
+    long long kernel_updates;   /* async: local iterations (sum of k_i) */
     int    teams;            /* async: concurrent slice teams used */
     long long copy_retries;  /* async: predecessor copies redone (slot overwritten meanwhile) */
     long long idle_rounds;   /* async: team rounds with nothing to update */

@@ -61,6 +61,8 @@ class pr_stats(ctypes.Structure):
         ("fine_ms", ctypes.c_double), ("coarse_ms", ctypes.c_double),
         ("fine_lups", ctypes.c_double), ("cg_iters", ctypes.c_longlong),
         ("g_solves", ctypes.c_longlong), ("g_skipped", ctypes.c_longlong),
+        ("kernel_ms", ctypes.c_double), ("kernel_cg_iters", ctypes.c_longlong),
+        ("kernel_updates", ctypes.c_longlong),
         ("teams", ctypes.c_int), ("copy_retries", ctypes.c_longlong),
         ("idle_rounds", ctypes.c_longlong),
     ]

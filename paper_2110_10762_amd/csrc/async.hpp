@@ -135,7 +135,7 @@ __device__ __forceinline__ void hdr_publish(SliceHdr *h, int ver, int k, int g_v
                                             double delta, double drift, double stale_ref) {
     const int s = h->seq;
     __hip_atomic_store(&h->seq, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __atomic_thread_fence(__ATOMIC_RELEASE);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(&h->k, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&h->g_ver, g_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&h->final_from, final_from, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -159,7 +159,7 @@ __device__ __forceinline__ bool hdr_read(const SliceHdr *h, HdrView &o) {
     o.delta = ld_relaxed(&h->delta);
     o.drift = ld_relaxed(&h->drift);
     o.stale_ref = ld_relaxed(&h->stale_ref);
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int s2 = __hip_atomic_load(&h->seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return s1 == s2;
 }
@@ -190,7 +190,7 @@ __device__ __forceinline__ void team_copy(const Team &tm, const Geom &g, const d
                                           double *__restrict__ dst) {
     const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
     const int w = wave_id();
-    for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+    for (long long c = cr.begin + w; c < cr.end; c += nwaves()) {
         const Point p = chunk_point(g, c);
         if (p.valid) dst[p.idx] = src[p.idx];
     }
@@ -211,8 +211,8 @@ __device__ bool team_fine(Team &tm, const AsyncArgs &a, const double *src, doubl
         const int steps_per = DIM == 2 ? D : 1;
         const int passes = (a.m + steps_per - 1) / steps_per;
         const double *cur = src;
-        const int waves = tm.size * WAVES_PER_BLOCK;
-        const int wid = tm.rank * WAVES_PER_BLOCK + wave_id();
+        const int waves = tm.size * nwaves();
+        const int wid = tm.rank * nwaves() + wave_id();
         for (int p = 0; p < passes; ++p) {
             double *tgt = ((passes - 1 - p) % 2 == 0) ? dst : scr;
             if constexpr (DIM == 2) {
@@ -274,12 +274,12 @@ __global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
     const int team = a.team_of[blockIdx.x];
     if (team < 0) return;
     const int rank = a.rank_of[blockIdx.x];
-    Team tm{a.tctr + team * 16, a.ctl, a.tsize[team], rank, 0u};
+    Team tm{a.tctr + (long long)team * team_counter_words(a.maxtsz), a.ctl, a.tsize[team], rank, 0u};
     long long *bc = a.tbc + team * 16;
     CGWork wk{a.cgr + (long long)team * a.npts, a.cgp0 + (long long)team * a.npts,
               a.cgp1 + (long long)team * a.npts, a.cgq + (long long)team * a.npts,
               a.tred + (long long)team * 2 * a.maxtsz};
-    __shared__ double lds[WAVES_PER_BLOCK];
+    __shared__ double lds[MAX_WAVES];
     const bool leader = (rank == 0 && threadIdx.x == 0);
     const long long np = a.npts;
     const long long all = (long long)(a.N + 1) * np;
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
                 if (leader) {
                     const double dr = a.slot_drift[(i - 1) * a.R + pv % a.R];
                     const int ff = __hip_atomic_load(&a.hdr[i - 1].final_from, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     const int after = (i == 1) ? pv : ld_acquire(&a.hdr[i - 1].ver);
                     c[0] = (a.mode == AMODE_REPLAY || after - pv <= a.R - 2) ? 1 : 0;
                     c[1] = __double_as_longlong(dr);
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
             {
                 const ChunkRange cr = team_chunks(a.g, tm.rank, tm.size);
                 const int w = wave_id();
-                for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+                for (long long c = cr.begin + w; c < cr.end; c += nwaves()) {
                     const Point p = chunk_point(a.g, c);
                     if (!p.valid) continue;
                     const double ln = v[p.idx] + (wv[p.idx] - w_old[p.idx]);

@@ -166,21 +166,28 @@ __device__ __forceinline__ Point chunk_point(const Geom &g, long long c) {
     return p;
 }
 
-// Sum of the 2d neighbour values of f (zero outside the domain), in the
-// order ((y-pair [+ z-pair]) + x-pair).
+// Sum of the 2d neighbour values (zero outside the domain), in the order
+// ((y-pair [+ z-pair]) + x-pair).  A chunk holds 64 consecutive x values of
+// one row, one per lane, so the x-neighbours come from the adjacent lanes by
+// DPP; only the chunk's end lanes load across the chunk border.  `center` is
+// the lane's own value (0 for lanes past the end of the row); f(j) loads the
+// value at index j.
 template <typename Fn>
-__device__ __forceinline__ double neighbour_sum(const Geom &g, const Point &p, Fn f) {
+__device__ __forceinline__ double neighbour_sum(const Geom &g, const Point &p, double center, Fn f) {
+    const int lane = threadIdx.x & (WAVE - 1);
     const long long n = g.n;
-    const double xl = p.x > 0 ? f(p.idx - 1) : 0.0;
-    const double xr = p.x + 1 < g.n ? f(p.idx + 1) : 0.0;
+    double xl = from_lower_lane(center);
+    double xr = from_upper_lane(center);
+    if (lane == 0) xl = p.x > 0 ? f(p.idx - 1) : 0.0;
+    if (lane == WAVE - 1) xr = (p.x + 1 < g.n) ? f(p.idx + 1) : 0.0;
     double s2 = 0.0;
     if (g.dim >= 2) {
-        const double yu = p.y > 0 ? f(p.idx - n) : 0.0;
-        const double yd = p.y + 1 < g.n ? f(p.idx + n) : 0.0;
+        const double yu = (p.valid && p.y > 0) ? f(p.idx - n) : 0.0;
+        const double yd = (p.valid && p.y + 1 < g.n) ? f(p.idx + n) : 0.0;
         s2 = yu + yd;
         if (g.dim == 3) {
-            const double zf = p.z > 0 ? f(p.idx - n * n) : 0.0;
-            const double zb = p.z + 1 < g.n ? f(p.idx + n * n) : 0.0;
+            const double zf = (p.valid && p.z > 0) ? f(p.idx - n * n) : 0.0;
+            const double zb = (p.valid && p.z + 1 < g.n) ? f(p.idx + n * n) : 0.0;
             s2 = s2 + (zf + zb);
         }
     }
@@ -200,27 +207,31 @@ struct CGWork {
 };
 
 // Solves (I - s h^2 L_h) x = b by CG with the team.  Returns the iteration
-// count, or -1 if the launch was aborted.  x and b must not alias.
+// count, or -1 if the launch was aborted.  x and b must not alias.  All
+// lanes of a wave run every chunk (lanes past the row end carry zeros) so
+// that the lane shifts see the whole chunk.
 __device__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
                        const double *__restrict__ b, double *__restrict__ x, const CGWork &wk) {
-    __shared__ double lds[WAVES_PER_BLOCK];
+    __shared__ double lds[MAX_WAVES];
     const double twod = 2.0 * g.dim;
     const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
     const int w = wave_id();
+    const int nw = nwaves();
     int par = 0;   // alternates the reduction slot arrays (write-after-read safety)
 
     // r = b - A b, x = b
     double rr_p = 0.0, bb_p = 0.0;
-    for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+    for (long long c = cr.begin + w; c < cr.end; c += nw) {
         const Point p = chunk_point(g, c);
-        if (!p.valid) continue;
-        const double bc = b[p.idx];
-        const double ns = neighbour_sum(g, p, [&](long long j) { return b[j]; });
-        const double rv = bc - be_point(bc, ns, twod, s);
-        x[p.idx] = bc;
-        wk.r[p.idx] = rv;
-        rr_p = __builtin_fma(rv, rv, rr_p);
-        bb_p = __builtin_fma(bc, bc, bb_p);
+        const double bc = p.valid ? b[p.idx] : 0.0;
+        const double ns = neighbour_sum(g, p, bc, [&](long long j) { return b[j]; });
+        if (p.valid) {
+            const double rv = bc - be_point(bc, ns, twod, s);
+            x[p.idx] = bc;
+            wk.r[p.idx] = rv;
+            rr_p = __builtin_fma(rv, rv, rr_p);
+            bb_p = __builtin_fma(bc, bc, bb_p);
+        }
     }
     double rr, bb;
     if (!team_reduce<false>(tm, bb_p, wk.red + par * tm.size, bb, lds)) return -1;
@@ -236,15 +247,16 @@ __device__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
     while (it < maxit && rr > thresh) {
         // phase A: p = r + beta p_old (also at neighbours), q = A p, <p, q>
         double pq_p = 0.0;
-        for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+        for (long long c = cr.begin + w; c < cr.end; c += nw) {
             const Point p = chunk_point(g, c);
-            if (!p.valid) continue;
             auto pn = [&](long long j) { return __builtin_fma(beta, pold[j], wk.r[j]); };
-            const double pc = pn(p.idx);
-            const double qv = be_point(pc, neighbour_sum(g, p, pn), twod, s);
-            pcur[p.idx] = pc;
-            wk.q[p.idx] = qv;
-            pq_p = __builtin_fma(pc, qv, pq_p);
+            const double pc = p.valid ? pn(p.idx) : 0.0;
+            const double qv = be_point(pc, neighbour_sum(g, p, pc, pn), twod, s);
+            if (p.valid) {
+                pcur[p.idx] = pc;
+                wk.q[p.idx] = qv;
+                pq_p = __builtin_fma(pc, qv, pq_p);
+            }
         }
         double pq;
         if (!team_reduce<false>(tm, pq_p, wk.red + par * tm.size, pq, lds)) return -1;
@@ -252,7 +264,7 @@ __device__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
         const double alpha = rr / pq;
         // phase B: x += alpha p, r -= alpha q, <r, r>
         double rn_p = 0.0;
-        for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+        for (long long c = cr.begin + w; c < cr.end; c += nw) {
             const Point p = chunk_point(g, c);
             if (!p.valid) continue;
             x[p.idx] = __builtin_fma(alpha, pcur[p.idx], x[p.idx]);

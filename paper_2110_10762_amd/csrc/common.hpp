@@ -11,6 +11,10 @@ namespace pr {
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;            // threads per workgroup for all kernels
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
+constexpr int MAX_WAVES = 16;         // largest workgroup: 1024 threads
+
+// Waves in this workgroup (uniform).
+__device__ __forceinline__ int nwaves() { return (int)(blockDim.x / WAVE); }
 
 // Index of this wave in its workgroup, as a wave-uniform (scalar) value so
 // that everything derived from it stays in scalar registers.
@@ -74,15 +78,15 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Block reduction in a fixed order; every thread gets the result.
 template <bool MAX>
-__device__ __forceinline__ double block_reduce(double v, double *lds /*[WAVES_PER_BLOCK]*/) {
+__device__ __forceinline__ double block_reduce(double v, double *lds /*[MAX_WAVES]*/) {
     v = MAX ? wave_max(v) : wave_sum(v);
     const int w = threadIdx.x / WAVE;
     __syncthreads();
     if ((threadIdx.x & (WAVE - 1)) == 0) lds[w] = v;
     __syncthreads();
     double t = lds[0];
-#pragma unroll
-    for (int i = 1; i < WAVES_PER_BLOCK; ++i) t = MAX ? fmax(t, lds[i]) : t + lds[i];
+    const int nw = nwaves();
+    for (int i = 1; i < nw; ++i) t = MAX ? fmax(t, lds[i]) : t + lds[i];
     return t;
 }
 
@@ -133,9 +137,16 @@ constexpr long long SPIN_LIMIT = 1ll << 27;   // ~ seconds of s_sleep(1) polling
 
 // Waits (single thread) until (int)(*ctr - target) >= 0.  Returns false if the
 // launch was aborted or the wait ran out (then the launch is aborted).
+__device__ __forceinline__ unsigned ld_relaxed(const unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Polls (single thread) with relaxed atomic loads until (int)(*ctr - target)
+// >= 0, then issues one agent-scope acquire fence.  Returns false if the
+// launch was aborted or the wait ran out (then the launch is aborted).
 __device__ __forceinline__ bool wait_counter(const unsigned *ctr, unsigned target, Control *ctl) {
     long long spins = 0;
-    while ((int)(ld_acquire(ctr) - target) < 0) {
+    while ((int)(ld_relaxed(ctr) - target) < 0) {
         if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
         if (++spins > SPIN_LIMIT) {
             __hip_atomic_store(&ctl->error, -7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -144,23 +155,33 @@ __device__ __forceinline__ bool wait_counter(const unsigned *ctr, unsigned targe
         }
         __builtin_amdgcn_s_sleep(1);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
 // A team is a fixed set of co-resident workgroups that cooperate on one
-// state.  Its barrier is a monotonically increasing arrival counter: the
-// e-th barrier completes when the counter reaches e * size.
+// state.  Its barrier counts arrivals on monotonically increasing counters:
+// workgroups are split into groups of at most TEAM_GROUP, each group has its
+// own counter on its own cache line, and the last arrival of a group bumps
+// the top counter; the e-th barrier completes when the top counter reaches
+// e * (number of groups).  Counter block layout (words): top at 0, group g at
+// 32 * (1 + g); team_counter_words() gives its size.
+constexpr int TEAM_GROUP = 32;
+
+__host__ __device__ inline int team_groups(int size) { return (size + TEAM_GROUP - 1) / TEAM_GROUP; }
+__host__ __device__ inline int team_counter_words(int size) { return 32 * (1 + team_groups(size)); }
+
 struct Team {
-    unsigned *ctr;    // arrival counter (zeroed before the launch)
+    unsigned *ctr;    // counter block (zeroed before the launch)
     Control *ctl;
     int size;         // workgroups in the team
     int rank;         // this workgroup's index in the team
     unsigned epoch;   // barriers passed so far (identical in all threads)
 };
 
-// Team barrier with agent-scope release/acquire.  Returns false if the launch
-// was aborted (every caller then unwinds).  All threads of all team
-// workgroups must call it.
+// Team barrier with agent-scope release/acquire ordering.  Returns false if
+// the launch was aborted (every caller then unwinds).  All threads of all
+// team workgroups must call it.
 __device__ __forceinline__ bool team_sync(Team &tm) {
     __shared__ int s_ok;
     tm.epoch += 1;
@@ -168,10 +189,21 @@ __device__ __forceinline__ bool team_sync(Team &tm) {
     if (threadIdx.x == 0) {
         bool ok = true;
         if (tm.size > 1) {
-            __hip_atomic_fetch_add(tm.ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            ok = wait_counter(tm.ctr, tm.epoch * (unsigned)tm.size, tm.ctl);
-        } else {
-            __atomic_thread_fence(__ATOMIC_SEQ_CST);
+            const int ng = team_groups(tm.size);
+            unsigned target;
+            if (ng == 1) {
+                __hip_atomic_fetch_add(tm.ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                target = tm.epoch * (unsigned)tm.size;
+            } else {
+                const int g = tm.rank / TEAM_GROUP;
+                const unsigned gsize = (unsigned)min(TEAM_GROUP, tm.size - g * TEAM_GROUP);
+                const unsigned old = __hip_atomic_fetch_add(tm.ctr + 32 * (1 + g), 1u, __ATOMIC_ACQ_REL,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                if (old + 1u == tm.epoch * gsize)
+                    __hip_atomic_fetch_add(tm.ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                target = tm.epoch * (unsigned)ng;
+            }
+            ok = wait_counter(tm.ctr, target, tm.ctl);
         }
         s_ok = ok && !__hip_atomic_load(&tm.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }

@@ -65,6 +65,7 @@ static int r1d_for(int n) {   // registers per lane for a 1D state
     return R;
 }
 static const int kMax1D = 32 * WAVE;   // 2048 points
+static const int SWEEP_BLOCK = 1024;   // threads per workgroup of the whole-GPU coarse sweeps
 
 // ------------------------------------------------------------------ handle
 struct Prob {
@@ -320,8 +321,8 @@ static int copy_dev(pr_problem *h, const double *src, double *dst, long long n) 
     return PR_OK;
 }
 
-static int coop_launch(pr_problem *h, const void *fn, int grid, void **args) {
-    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BLOCK), args, 0, h->stream);
+static int coop_launch(pr_problem *h, const void *fn, int grid, int block, void **args) {
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, h->stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(PR_ENORESIDENT, "cooperative launch of %d workgroups failed: %s", grid, hipGetErrorString(e));
@@ -375,12 +376,12 @@ static int run_sweep(pr_problem *h, const Prob &P, SweepArgs a) {
         HIPCHK(hipGetLastError());
         return PR_OK;
     }
-    int rc = zero_words(h, h->ctr, 64);
+    int rc = zero_words(h, h->ctr, team_counter_words(h->sweep_grid));
     if (rc) return rc;
     rc = zero_words(h, h->ctl, sizeof(Control) / 4);
     if (rc) return rc;
     void *args[] = {&a};
-    return coop_launch(h, (const void *)k_sweep_cg, h->sweep_grid, args);
+    return coop_launch(h, (const void *)k_sweep_cg, h->sweep_grid, SWEEP_BLOCK, args);
 }
 
 // ------------------------------------------------------------------ create / destroy
@@ -456,12 +457,12 @@ extern "C" int pr_create(const pr_config *cfgs, int nproblems, int device, void 
     for (int i = 0; i < 6; ++i)
         if (hipEventCreate(&h->ev[i]) != hipSuccess) return bail(fail(PR_EHIP, "hipEventCreate failed"));
     int rc;
-    if ((rc = alloc_t(h, &h->ctr, 64))) return bail(rc);
+    if ((rc = alloc_t(h, &h->ctr, 4096))) return bail(rc);
     if ((rc = alloc_t(h, &h->ctl, 1))) return bail(rc);
     if ((rc = alloc_t(h, &h->dscal, 16))) return bail(rc);
     if ((rc = alloc_t(h, &h->iscal, 16))) return bail(rc);
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_sweep_cg, BLOCK, 0) != hipSuccess || occ < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_sweep_cg, SWEEP_BLOCK, 0) != hipSuccess || occ < 1)
         return bail(fail(PR_EHIP, "occupancy query failed"));
     h->sweep_grid = h->ncu * std::min(occ, 1);
     h->red_slots = 2 * 4096;
@@ -571,6 +572,8 @@ static void stats_reset(pr_stats *st) {
     st->fine_lups = 0;
     st->cg_iters = st->g_solves = st->g_skipped = 0;
     st->teams = 0;
+    st->kernel_ms = 0;
+    st->kernel_cg_iters = st->kernel_updates = 0;
     st->copy_retries = st->idle_rounds = 0;
 }
 
@@ -616,7 +619,7 @@ extern "C" int pr_apply_coarse(pr_problem *h, const double *in, double *out, int
         HIPCHK(hipStreamSynchronize(h->stream));
         return PR_OK;
     }
-    if ((rc = zero_words(h, h->ctr, 64))) return rc;
+    if ((rc = zero_words(h, h->ctr, team_counter_words(h->sweep_grid)))) return rc;
     if ((rc = zero_words(h, h->ctl, sizeof(Control) / 4))) return rc;
     if ((rc = zero_words(h, h->iscal, 2))) return rc;
     long long npts = P.npts;
@@ -628,7 +631,7 @@ extern "C" int pr_apply_coarse(pr_problem *h, const double *in, double *out, int
     Control *ctl = h->ctl;
     unsigned long long *ci = h->iscal;
     void *args[] = {&in, &out, &npts, &count, &g, &s, &tol, &maxit, &wk, &ctr, &ctl, &ci};
-    if ((rc = coop_launch(h, (const void *)k_coarse_cg_batch, h->sweep_grid, args))) return rc;
+    if ((rc = coop_launch(h, (const void *)k_coarse_cg_batch, h->sweep_grid, SWEEP_BLOCK, args))) return rc;
     if ((rc = check_control(h))) return rc;
     unsigned long long its = 0;
     HIPCHK(hipMemcpy(&its, h->iscal, sizeof its, hipMemcpyDeviceToHost));

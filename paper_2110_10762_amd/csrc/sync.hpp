@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64) void k_sweep_1d(SweepArgs a) {
 }
 
 // Cooperative launch: the whole grid is one team.
-__global__ __launch_bounds__(BLOCK) void k_sweep_cg(SweepArgs a) {
+__global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
     Team tm{a.ctr, a.ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
     const ChunkRange cr = team_chunks(a.g, tm.rank, tm.size);
     const int w = wave_id();
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cg(SweepArgs a) {
             if (it < 0) return;
             its += (unsigned long long)it;
         }
-        for (long long c = cr.begin + w; c < cr.end; c += WAVES_PER_BLOCK) {
+        for (long long c = cr.begin + w; c < cr.end; c += nwaves()) {
             const Point p = chunk_point(a.g, c);
             if (!p.valid) continue;
             if (a.init) {
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cg(SweepArgs a) {
         }
         if (!team_sync(tm)) return;
     }
-    __shared__ double lds[WAVES_PER_BLOCK];
+    __shared__ double lds[MAX_WAVES];
     dmax = block_reduce<true>(dmax, lds);
     if (threadIdx.x == 0) {
         if (!a.init) atomic_max_nonneg(a.delta, dmax);
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_cg(SweepArgs a) {
 
 // Batch of independent coarse solves (tests and the apply entry point):
 // state c of the batch is solved by the whole grid, one after the other.
-__global__ __launch_bounds__(BLOCK) void k_coarse_cg_batch(const double *src, double *dst, long long npts,
+__global__ __launch_bounds__(1024) void k_coarse_cg_batch(const double *src, double *dst, long long npts,
                                                            int count, Geom g, double s, double tol,
                                                            int maxit, CGWork wk, unsigned *ctr,
                                                            Control *ctl, unsigned long long *cg_iters) {
