@@ -281,3 +281,58 @@ def fine_shapes(dim: int):
         _check(lib.pr_fine_shape_get(dim, i, ctypes.byref(d), ctypes.byref(r), ctypes.byref(x)))
         out.append((d.value, r.value, x.value))
     return out
+
+
+# ---------------------------------------------------------------------- autograd
+
+def _torch_function():
+    import torch
+
+    class HeatPararealFn(torch.autograd.Function):
+        """u(T) = Parareal solution of the heat problem from u0 with diffusivity nu.
+
+        forward: synchronous (default), asynchronous or serial-fine solve;
+        the slice-boundary values lambda_0..lambda_N are kept as checkpoints.
+        backward: pr_grad (adjoint of the fine integration with in-slice
+        recomputation) gives dL/du0 and dL/dnu for the upstream dL/du(T).
+        The fine step dt is fixed by the slicing, independent of nu."""
+
+        @staticmethod
+        def forward(ctx, u0, nu, dim, n, T, nslices, dt_nominal, eps, driver):
+            cfg = make_config(dim, n, float(nu), T, nslices, dt_nominal, eps=eps)
+            prob = Problem(cfg, device=u0.device.index or 0)
+            lam = torch.empty((nslices + 1,) + tuple(u0.shape), dtype=torch.float64, device=u0.device)
+            u = u0.detach().contiguous()
+            if driver == "sync":
+                prob.solve_sync(u, lam)
+            elif driver == "async":
+                prob.solve_async(u, lam)
+            elif driver == "fine":
+                prob.solve_fine(u, lam)
+            else:
+                raise ValueError("driver must be 'sync', 'async' or 'fine'")
+            ctx.prob = prob
+            ctx.nu_shape = nu.shape
+            ctx.save_for_backward(lam)
+            return lam[-1].clone()
+
+        @staticmethod
+        def backward(ctx, gT):
+            (lam,) = ctx.saved_tensors
+            d0 = torch.empty_like(gT, dtype=torch.float64).contiguous()
+            dnu = ctx.prob.grad(lam, gT.to(torch.float64).contiguous(), d0)
+            gnu = torch.full(ctx.nu_shape, dnu, dtype=torch.float64, device=gT.device)
+            return d0, gnu, None, None, None, None, None, None, None
+
+    return HeatPararealFn
+
+
+_HPF = None
+
+
+def heat_parareal(u0, nu, dim, n, T, nslices, dt_nominal, eps=1e-10, driver="sync"):
+    """Differentiable u(T) (see HeatPararealFn)."""
+    global _HPF
+    if _HPF is None:
+        _HPF = _torch_function()
+    return _HPF.apply(u0, nu, dim, n, T, nslices, dt_nominal, eps, driver)
