@@ -171,6 +171,16 @@ int  pr_apply_coarse(pr_problem *h, const double *in, double *out, int count, lo
 /* Fine-kernel shape control (autotuner and tests): the supported shapes are
  * enumerated by index; pr_set_fine_shape selects one for a problem. */
 int  pr_fine_shape_count(int dim);
+/* Project autotuner: times every fine-kernel shape for this problem's state
+ * size (problem >= 0: its N states and, separately, the single state of the
+ * serial fine run; problem == -1: every grid side of a batch) over m steps,
+ * `reps` timed runs each, and selects the fastest.  Results are cached per
+ * process and, if the environment variable PR_TUNE_CACHE names a file, in
+ * that file.  Outputs (may be NULL): the chosen depth / rows and its time. */
+int  pr_autotune(pr_problem *h, int problem, int reps, int *tb_depth, int *tile_rows, double *best_ms);
+/* Batched handles: capture one iteration of the whole batch as a hipGraph
+ * and replay it (enable = 1, the default) or launch it directly (0). */
+int  pr_set_graph(pr_problem *h, int enable);
 int  pr_fine_shape_get(int dim, int index, int *tb_depth, int *tile_rows, int *xpts);
 int  pr_set_fine_shape(pr_problem *h, int problem, int tb_depth, int tile_rows);
 

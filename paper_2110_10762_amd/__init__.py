@@ -80,7 +80,7 @@ EXPORTS = [
     "pr_create", "pr_destroy", "pr_last_error", "pr_get_info", "pr_solve_sync",
     "pr_set_async_options", "pr_solve_async", "pr_solve_fine", "pr_grad",
     "pr_apply_fine", "pr_apply_coarse", "pr_fine_shape_count", "pr_fine_shape_get",
-    "pr_set_fine_shape",
+    "pr_set_fine_shape", "pr_autotune", "pr_set_graph",
 ]
 
 _lib = None
@@ -109,6 +109,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pr_fine_shape_count.argtypes = [ctypes.c_int]
     lib.pr_fine_shape_get.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3
     lib.pr_set_fine_shape.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.pr_autotune.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    lib.pr_set_graph.argtypes = [P, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -271,6 +274,22 @@ class Problem:
 
     def set_fine_shape(self, tb_depth: int, tile_rows: int, problem: int = 0):
         _check(self.lib.pr_set_fine_shape(self.h, problem, tb_depth, tile_rows))
+
+    def autotune(self, problem: int = 0, reps: int = 3):
+        """Runs the library's autotuner; returns (tb_depth, tile_rows, best_ms)."""
+        d, r, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(self.lib.pr_autotune(self.h, problem, reps, ctypes.byref(d), ctypes.byref(r), ctypes.byref(ms)))
+        return d.value, r.value, ms.value
+
+    def set_graph(self, enable: bool):
+        _check(self.lib.pr_set_graph(self.h, 1 if enable else 0))
+
+    def solve_batch(self, u0, lam, allow_notconv=False):
+        """Batched synchronous solve; returns one Stats per problem."""
+        arr = (pr_stats * self.nproblems)()
+        rc = _check(self.lib.pr_solve_sync(self.h, _ptr(u0), _ptr(lam), arr),
+                    (PR_ENOTCONV,) if allow_notconv else ())
+        return rc, [arr[b] for b in range(self.nproblems)]
 
 
 def fine_shapes(dim: int):

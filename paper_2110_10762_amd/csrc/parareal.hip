@@ -71,6 +71,7 @@ static const int SWEEP_BLOCK = 1024;   // threads per workgroup of the whole-GPU
 struct Prob {
     pr_config cfg;
     int dim, n, N, m;
+    int shape1 = -1;       // fine-kernel shape for single-state runs (serial fine), -1: same
     double nu, T, h, dT, dt, r, s;
     long long npts;
     long long off_state;   // offset of this problem's state in concatenated u0
@@ -113,6 +114,7 @@ struct pr_problem {
     // batched workspace
     BatchWork bw{};
     bool bw_ready = false;
+    bool bw_dirty = false;
     // adjoint workspace
     AdjWork jw{};
     bool jw_ready = false;
@@ -648,8 +650,13 @@ extern "C" int pr_solve_fine(pr_problem *h, const double *u0, double *lam, pr_st
     stats_reset(st);
     HIPCHK(hipEventRecord(h->ev[0], h->stream));
     if ((rc = copy_dev(h, u0, lam, P.npts))) return rc;
+    Prob P1 = P;   // single-state runs may use their own tuned shape
+    if (P.shape1 >= 0) P1.shape = P.shape1;
+    const int passes1 = (P.m + fine_depth(P1) - 1) / fine_depth(P1);
+    if (P.dim > 1 && passes1 > 1 && !h->tmp)
+        if ((rc = alloc_t(h, &h->tmp, (size_t)(P.N + 1) * P.npts))) return rc;
     for (int i = 1; i <= P.N; ++i)
-        if ((rc = run_fine(h, P, lam + (long long)(i - 1) * P.npts, lam + (long long)i * P.npts, h->tmp, 1, P.m,
+        if ((rc = run_fine(h, P1, lam + (long long)(i - 1) * P.npts, lam + (long long)i * P.npts, h->tmp, 1, P.m,
                            P.npts, P.npts)))
             return rc;
     HIPCHK(hipEventRecord(h->ev[1], h->stream));
@@ -663,6 +670,8 @@ extern "C" int pr_solve_fine(pr_problem *h, const double *u0, double *lam, pr_st
 }
 
 // ------------------------------------------------------------------ synchronous Parareal
+static int batched_solve_sync(pr_problem *h, const double *u0, double *lam, pr_stats *st);
+
 extern "C" int pr_solve_sync(pr_problem *h, const double *u0, double *lam, pr_stats *st) {
     if (h && h->P.size() > 1) return batched_solve_sync(h, u0, lam, st);
     int rc = need_single(h);

@@ -1,0 +1,100 @@
+"""Batched synchronous Parareal (many uneven 2D problems, one persistent
+coarse-sweep launch per iteration, hipGraph replay) vs the oracle and vs the
+single-problem path."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import heat, parareal, spectral
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2110_10762_amd as pr  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def disc_of(p):
+    return heat.discretise(p.dim, p.n, p.nu, p.T, p.nslices, p.dt_nominal)
+
+
+def run_batch(probs, graph=True, tune=False):
+    h = pr.Problem([pr.config_of(p) for p in probs])
+    if tune:
+        h.autotune(-1, reps=1)
+    h.set_graph(graph)
+    u0 = torch.from_numpy(np.concatenate([p.u0.ravel() for p in probs])).to(DEV)
+    total = sum((p.nslices + 1) * p.n * p.n for p in probs)
+    lam = torch.empty(total, dtype=torch.float64, device=DEV)
+    rc, st = h.solve_batch(u0, lam)
+    out, off = [], 0
+    for p in probs:
+        sz = (p.nslices + 1) * p.n * p.n
+        out.append(lam[off: off + sz].reshape(p.nslices + 1, p.n, p.n).cpu().numpy())
+        off += sz
+    return out, st
+
+
+def small_batch():
+    return workloads.batched(count=12, sides=(32, 48, 64), max_slices=10)
+
+
+def test_batched_vs_oracle_and_single():
+    probs = small_batch()
+    out, st = run_batch(probs)
+    for b, p in enumerate(probs):
+        d = disc_of(p)
+        assert d.m == 64
+        props = heat.Propagators(d, cg_tol=p.cg_tol)
+        ref = parareal.parareal_sync(p.u0, props.F, props.G, d.nslices, eps=p.eps)
+        assert st[b].converged == 1
+        assert st[b].iters == ref.iters, b
+        assert rel(out[b], ref.lam) <= 1e-10, b
+        single = pr.Problem(pr.config_of(p))
+        lam = torch.empty((p.nslices + 1, p.n, p.n), dtype=torch.float64, device=DEV)
+        s1 = pr.Stats(p.nslices, p.nslices + 1)
+        single.solve_sync(torch.from_numpy(p.u0).to(DEV), lam, s1)
+        assert s1.iters == st[b].iters
+        assert rel(out[b], lam.cpu().numpy()) <= 1e-10
+
+
+def test_graph_replay_equals_direct_launch():
+    probs = small_batch()
+    a, sa = run_batch(probs, graph=True)
+    b, sb = run_batch(probs, graph=False)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert [s.iters for s in sa] == [s.iters for s in sb]
+
+
+def test_autotuned_batch_matches():
+    probs = small_batch()
+    a, _ = run_batch(probs)
+    b, _ = run_batch(probs, tune=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)     # every fine-kernel shape computes the same values
+
+
+def test_full_batch_sampled():
+    # the 512-problem workload; a seeded sample of 16 problems (always the
+    # smallest and the largest) is checked against the exact-G closed form at
+    # the iteration the GPU stopped
+    probs = workloads.batched()
+    out, st = run_batch(probs, tune=True)
+    work = [p.nslices * p.n * p.n for p in probs]
+    rng = np.random.default_rng(7)
+    pick = set(rng.choice(len(probs), 14, replace=False).tolist())
+    pick |= {int(np.argmin(work)), int(np.argmax(work))}
+    for b in sorted(pick):
+        p = probs[b]
+        d = disc_of(p)
+        assert st[b].converged == 1, b
+        want = spectral.parareal_sync(p.u0, d.r, d.m, d.s, st[b].iters, range(p.nslices + 1))
+        assert rel(out[b], want) <= 1e-9, (b, rel(out[b], want))
+        star = spectral.serial_fine(p.u0, d.r, d.m, d.nslices, slices=[d.nslices])[0]
+        assert rel(out[b][-1], star) <= 1e-9, b
