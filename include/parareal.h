@@ -70,6 +70,10 @@ typedef struct pr_config {
     int    kmax;         /* iteration cap; <= 0 or > N means N (finite termination) */
     int    tb_depth;     /* fine steps per HBM pass (temporal block depth); 0 = tuned */
     int    tile_rows;    /* rows per register strip of the fine kernel; 0 = tuned */
+    int    coarse_increment; /* 0: G(new) - G(old) as written in eq. (pr) / Algorithm 2;
+                                1: G applied to the change new - old (G is linear, Section 3.1),
+                                CG from 0 to an absolute residual tol*||new||; an unchanged input
+                                gives exactly 0.  Fewer CG iterations, same fixed point. */
 } pr_config;
 
 /* Derived discretisation of one problem (read-only view). */

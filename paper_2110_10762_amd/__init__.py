@@ -38,7 +38,7 @@ class pr_config(ctypes.Structure):
         ("T", ctypes.c_double), ("nslices", ctypes.c_int), ("dt_nominal", ctypes.c_double),
         ("coarse", ctypes.c_int), ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
         ("eps", ctypes.c_double), ("kmax", ctypes.c_int), ("tb_depth", ctypes.c_int),
-        ("tile_rows", ctypes.c_int),
+        ("tile_rows", ctypes.c_int), ("coarse_increment", ctypes.c_int),
     ]
 
 
@@ -145,9 +145,10 @@ def _ptr(x) -> int:
 
 
 def make_config(dim, n, nu, T, nslices, dt_nominal, coarse=PR_COARSE_AUTO, cg_tol=1e-12,
-                cg_maxit=0, eps=1e-10, kmax=0, tb_depth=0, tile_rows=0) -> pr_config:
+                cg_maxit=0, eps=1e-10, kmax=0, tb_depth=0, tile_rows=0,
+                coarse_increment=0) -> pr_config:
     return pr_config(dim, n, nu, T, nslices, dt_nominal, coarse, cg_tol, cg_maxit, eps, kmax,
-                     tb_depth, tile_rows)
+                     tb_depth, tile_rows, coarse_increment)
 
 
 def config_of(problem, **over) -> pr_config:

@@ -89,6 +89,7 @@ struct AsyncArgs {
     int cg_maxit;
     Geom g;
     int mode, R, L, idle_skip;
+    int incr;                // coarse solves act on the change of their input
     double *ring;            // [R][(N+1) npts]
     double *X, *W;           // [2][(N+1) npts]
     double *V, *S;           // [(N+1) npts]; S only if a slice needs several fine passes
@@ -241,7 +242,8 @@ __device__ bool team_fine(Team &tm, const AsyncArgs &a, const double *src, doubl
 
 // ---- coarse solve of one state by a team; returns iterations or -1
 template <int DIM, int RR>
-__device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double *x, const CGWork &wk) {
+__device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double *x, const CGWork &wk,
+                           double abs_thresh2 = -1.0) {
     if constexpr (DIM == 1) {
         if (wave_id() == 0) {
             double v[RR], inv[RR];
@@ -261,7 +263,7 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
         }
         return team_sync(tm) ? 0 : -1;
     } else {
-        const int it = cg_team(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk);
+        const int it = cg_team(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
         if (it < 0) return -1;
         return team_sync(tm) ? it : -1;
     }
@@ -275,6 +277,7 @@ __global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
     if (team < 0) return;
     const int rank = a.rank_of[blockIdx.x];
     Team tm{a.tctr + (long long)team * team_counter_words(a.maxtsz), a.ctl, a.tsize[team], rank, 0u};
+    if (!team_setup(tm)) return;
     long long *bc = a.tbc + team * 16;
     CGWork wk{a.cgr + (long long)team * a.npts, a.cgp0 + (long long)team * a.npts,
               a.cgp1 + (long long)team * a.npts, a.cgq + (long long)team * a.npts,
@@ -370,6 +373,9 @@ __global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
             // ---------------- newest predecessor (FREE/EXACT read it after F)
             double drift_read = 0.0;
             int g_final = 0;
+            double nrm_part = 0.0;
+            double *dbuf = a.W + i * np;          // increment mode: change of the input
+            double *ybuf = a.W + all + i * np;    // increment mode: G(change)
             for (;;) {
                 if (a.mode != AMODE_REPLAY) {
                     long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -383,7 +389,21 @@ __global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
                 }
                 if (stale) break;
                 const double *src = a.ring + (long long)(pv % a.R) * all + (i - 1) * np;
-                team_copy(tm, a.g, src, x_new);
+                if (a.incr) {
+                    // x_new = copy, d = x_new - x_old, ||x_new||^2 (reduced once the copy is valid)
+                    nrm_part = 0.0;
+                    const ChunkRange cr = team_chunks(a.g, tm.rank, tm.size);
+                    for (long long cc = cr.begin + wave_id(); cc < cr.end; cc += nwaves()) {
+                        const Point p = chunk_point(a.g, cc);
+                        if (!p.valid) continue;
+                        const double xv = src[p.idx];
+                        x_new[p.idx] = xv;
+                        dbuf[p.idx] = xv - x_old[p.idx];
+                        nrm_part = __builtin_fma(xv, xv, nrm_part);
+                    }
+                } else {
+                    team_copy(tm, a.g, src, x_new);
+                }
                 long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                 if (leader) {
                     const double dr = a.slot_drift[(i - 1) * a.R + pv % a.R];
@@ -408,10 +428,17 @@ __global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
                     goto out;
                 }
             }
-            // ---------------- w_new = G(x_new), or reuse w_old
+            // ---------------- w_new = G(x_new) (or G(x_new - x_old)), or nothing if stale
             const double *wv = w_old;
             if (!stale) {
-                const int it = team_coarse<DIM, RR>(tm, a, x_new, w_new, wk);
+                int it;
+                if (a.incr) {
+                    double nrm = 0.0;
+                    if (!team_reduce<false>(tm, nrm_part, wk.red, nrm, lds)) goto out;
+                    it = team_coarse<DIM, RR>(tm, a, dbuf, ybuf, wk, a.cg_tol * a.cg_tol * nrm);
+                } else {
+                    it = team_coarse<DIM, RR>(tm, a, x_new, w_new, wk);
+                }
                 if (it < 0) goto out;
                 cg_its += (unsigned long long)it;
                 ++g_solves;
@@ -430,13 +457,14 @@ __global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
                 for (long long c = cr.begin + w; c < cr.end; c += nwaves()) {
                     const Point p = chunk_point(a.g, c);
                     if (!p.valid) continue;
-                    const double ln = v[p.idx] + (wv[p.idx] - w_old[p.idx]);
+                    const double ln = a.incr ? v[p.idx] + (stale ? 0.0 : ybuf[p.idx])
+                                             : v[p.idx] + (wv[p.idx] - w_old[p.idx]);
                     dmax = fmax(dmax, fabs(ln - cur[p.idx]));
                     nxt[p.idx] = ln;
                 }
             }
             double delta;
-            if (!team_reduce<true>(tm, dmax, wk.red + (tm.epoch & 1) * tm.size, delta, lds)) goto out;
+            if (!team_reduce<true>(tm, dmax, wk.red, delta, lds)) goto out;
             // ---------------- publish (leader), update the slice's control state
             if (leader) {
                 SliceLoc &L = a.loc[i];
@@ -450,7 +478,7 @@ __global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
                 hdr_publish(h, myver + 1, h->k + 1, pv, ff, delta, drift, sref);
                 if (!stale) {
                     L.xo ^= 1;
-                    L.wo ^= 1;
+                    if (!a.incr) L.wo ^= 1;
                 }
                 L.f_ver = pv;
                 L.f_final = gf;

@@ -20,13 +20,15 @@
 // applied across independent problems.
 #pragma once
 #include "fine.hpp"
-#include "coarse.hpp"
+#include "sync.hpp"
 
 namespace pr {
 
 struct BProb {
     int n, N, m, passes;   // grid side, slices, fine steps per slice, fine passes per slice
     int kmax, cg_maxit;
+    int incr;              // coarse solves on the change of their input
+    int pad;
     long long npts;
     long long off_lam;     // offset of lambda_0 in the concatenated iterate (and in v, w, tmp)
     double r, s, eps, cg_tol;
@@ -52,7 +54,7 @@ struct BatchArgs {
     unsigned *tctr;
     long long *tbc;
     double *tred;
-    double *wn, *cgr, *cgp0, *cgp1, *cgq;   // [nteams][maxnpts]
+    double *wn, *cgr, *cgp0, *cgp1, *cgq, *d0, *d1;   // [nteams][maxnpts]
     long long maxnpts;
     const int *order;
     unsigned *queue;
@@ -86,6 +88,7 @@ __global__ __launch_bounds__(BLOCK) void k_bsweep(BatchArgs a) {
     const int team = a.team_of[blockIdx.x];
     if (team < 0) return;
     Team tm{a.tctr + (long long)team * a.ctr_stride, a.ctl, a.tsz, a.rank_of[blockIdx.x], 0u};
+    if (!team_setup(tm)) return;
     long long *bc = a.tbc + team * 16;
     double *wn = a.wn + team * a.maxnpts;
     CGWork wk{a.cgr + team * a.maxnpts, a.cgp0 + team * a.maxnpts, a.cgp1 + team * a.maxnpts,
@@ -113,42 +116,15 @@ __global__ __launch_bounds__(BLOCK) void k_bsweep(BatchArgs a) {
         if (!S.active) continue;
         const int k = S.k;
         const bool init = (k == 0);
-        double *lam = a.lam + P.off_lam;
-        double *w = a.w + P.off_lam;
-        const double *v = a.v + P.off_lam;
-        const ChunkRange cr = team_chunks(P.g, tm.rank, tm.size);
         double dmax = 0.0;
         unsigned long long its = 0;
-        for (int i = init ? 1 : k; i <= P.N; ++i) {
-            const bool skip = (!init && i == k);
-            if (!skip) {
-                const int it = cg_team(tm, P.g, P.s, P.cg_tol, P.cg_maxit, lam + (long long)(i - 1) * P.npts, wn, wk);
-                if (it < 0) return;
-                its += (unsigned long long)it;
-            }
-            double *li = lam + (long long)i * P.npts;
-            double *wi = w + (long long)i * P.npts;
-            const double *vi = v + (long long)i * P.npts;
-            for (long long cc = cr.begin + wave_id(); cc < cr.end; cc += nwaves()) {
-                const Point p = chunk_point(P.g, cc);
-                if (!p.valid) continue;
-                if (init) {
-                    const double wv = wn[p.idx];
-                    li[p.idx] = wv;
-                    wi[p.idx] = wv;
-                } else {
-                    const double wold = wi[p.idx];
-                    const double wv = skip ? wold : wn[p.idx];
-                    const double ln = vi[p.idx] + (wv - wold);
-                    dmax = fmax(dmax, fabs(ln - li[p.idx]));
-                    li[p.idx] = ln;
-                    wi[p.idx] = wv;
-                }
-            }
-            if (!team_sync(tm)) return;
-        }
+        const SweepBufs SB{a.lam + P.off_lam, a.v + P.off_lam, a.w + P.off_lam, wn,
+                           a.d0 + team * a.maxnpts, a.d1 + team * a.maxnpts};
+        if (!team_coarse_sweep(tm, P.g, P.s, P.cg_tol, P.cg_maxit, P.npts, init ? 1 : k, P.N, init ? -1 : k, init,
+                               P.incr != 0, SB, wk, dmax, its, lds))
+            return;
         double delta = 0.0;
-        if (!team_reduce<true>(tm, dmax, wk.red + (tm.epoch & 1) * tm.size, delta, lds)) return;
+        if (!team_reduce<true>(tm, dmax, wk.red, delta, lds)) return;
         if (leader) {
             S.cg_iters += its;
             if (init) {
@@ -188,6 +164,7 @@ struct BatchWork {
     unsigned *tctr = nullptr, *queue = nullptr;
     long long *tbc = nullptr;
     double *tred = nullptr, *wn = nullptr, *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr, *cgq = nullptr;
+    double *d0 = nullptr, *d1 = nullptr;
     long long maxnpts = 0, total = 0;
     int nteams = 0, tsz = 0, grid = 0;
     // per size class: side, units, fine shape

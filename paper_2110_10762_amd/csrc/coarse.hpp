@@ -210,37 +210,55 @@ struct CGWork {
 // count, or -1 if the launch was aborted.  x and b must not alias.  All
 // lanes of a wave run every chunk (lanes past the row end carry zeros) so
 // that the lane shifts see the whole chunk.
+//   abs_thresh2 < 0: x0 = b, stop at ||r||^2 <= tol^2 ||b||^2 (the coarse
+//                    propagator applied to a state);
+//   abs_thresh2 >= 0: x0 = 0, stop at ||r||^2 <= abs_thresh2 (applied to the
+//                    change of a state: a zero right-hand side returns 0).
 __device__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
-                       const double *__restrict__ b, double *__restrict__ x, const CGWork &wk) {
+                       const double *__restrict__ b, double *__restrict__ x, const CGWork &wk,
+                       double abs_thresh2 = -1.0) {
     __shared__ double lds[MAX_WAVES];
     const double twod = 2.0 * g.dim;
     const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
     const int w = wave_id();
     const int nw = nwaves();
-    int par = 0;   // alternates the reduction slot arrays (write-after-read safety)
+    double *__restrict__ r = wk.r;
+    double *__restrict__ q = wk.q;
+    const bool from_zero = abs_thresh2 >= 0.0;
 
-    // r = b - A b, x = b
     double rr_p = 0.0, bb_p = 0.0;
     for (long long c = cr.begin + w; c < cr.end; c += nw) {
         const Point p = chunk_point(g, c);
         const double bc = p.valid ? b[p.idx] : 0.0;
-        const double ns = neighbour_sum(g, p, bc, [&](long long j) { return b[j]; });
-        if (p.valid) {
-            const double rv = bc - be_point(bc, ns, twod, s);
-            x[p.idx] = bc;
-            wk.r[p.idx] = rv;
-            rr_p = __builtin_fma(rv, rv, rr_p);
-            bb_p = __builtin_fma(bc, bc, bb_p);
+        if (from_zero) {                       // r = b, x = 0
+            if (p.valid) {
+                x[p.idx] = 0.0;
+                r[p.idx] = bc;
+                rr_p = __builtin_fma(bc, bc, rr_p);
+            }
+        } else {                               // r = b - A b, x = b
+            const double ns = neighbour_sum(g, p, bc, [&](long long j) { return b[j]; });
+            if (p.valid) {
+                const double rv = bc - be_point(bc, ns, twod, s);
+                x[p.idx] = bc;
+                r[p.idx] = rv;
+                rr_p = __builtin_fma(rv, rv, rr_p);
+                bb_p = __builtin_fma(bc, bc, bb_p);
+            }
         }
     }
-    double rr, bb;
-    if (!team_reduce<false>(tm, bb_p, wk.red + par * tm.size, bb, lds)) return -1;
-    par ^= 1;
-    if (!team_reduce<false>(tm, rr_p, wk.red + par * tm.size, rr, lds)) return -1;
-    par ^= 1;
-    const double thresh = tol * tol * bb;
+    double rr, thresh;
+    if (from_zero) {
+        if (!team_reduce<false>(tm, rr_p, wk.red, rr, lds)) return -1;
+        thresh = abs_thresh2 > 0.0 ? abs_thresh2 : tol * tol * rr;
+    } else {
+        double bb;
+        if (!team_reduce<false>(tm, bb_p, wk.red, bb, lds)) return -1;
+        if (!team_reduce<false>(tm, rr_p, wk.red, rr, lds)) return -1;
+        thresh = tol * tol * bb;
+    }
 
-    const double *pold = wk.r;   // first direction: p = r (beta = 0)
+    const double *pold = r;   // first direction: p = r (beta = 0)
     double beta = 0.0;
     double *pcur = wk.p0;
     int it = 0;
@@ -249,18 +267,17 @@ __device__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
         double pq_p = 0.0;
         for (long long c = cr.begin + w; c < cr.end; c += nw) {
             const Point p = chunk_point(g, c);
-            auto pn = [&](long long j) { return __builtin_fma(beta, pold[j], wk.r[j]); };
+            auto pn = [&](long long j) { return __builtin_fma(beta, pold[j], r[j]); };
             const double pc = p.valid ? pn(p.idx) : 0.0;
             const double qv = be_point(pc, neighbour_sum(g, p, pc, pn), twod, s);
             if (p.valid) {
                 pcur[p.idx] = pc;
-                wk.q[p.idx] = qv;
+                q[p.idx] = qv;
                 pq_p = __builtin_fma(pc, qv, pq_p);
             }
         }
         double pq;
-        if (!team_reduce<false>(tm, pq_p, wk.red + par * tm.size, pq, lds)) return -1;
-        par ^= 1;
+        if (!team_reduce<false>(tm, pq_p, wk.red, pq, lds)) return -1;
         const double alpha = rr / pq;
         // phase B: x += alpha p, r -= alpha q, <r, r>
         double rn_p = 0.0;
@@ -268,13 +285,12 @@ __device__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
             const Point p = chunk_point(g, c);
             if (!p.valid) continue;
             x[p.idx] = __builtin_fma(alpha, pcur[p.idx], x[p.idx]);
-            const double rv = __builtin_fma(-alpha, wk.q[p.idx], wk.r[p.idx]);
-            wk.r[p.idx] = rv;
+            const double rv = __builtin_fma(-alpha, q[p.idx], r[p.idx]);
+            r[p.idx] = rv;
             rn_p = __builtin_fma(rv, rv, rn_p);
         }
         double rn;
-        if (!team_reduce<false>(tm, rn_p, wk.red + par * tm.size, rn, lds)) return -1;
-        par ^= 1;
+        if (!team_reduce<false>(tm, rn_p, wk.red, rn, lds)) return -1;
         beta = rn / rr;
         rr = rn;
         pold = pcur;

@@ -160,16 +160,26 @@ __device__ __forceinline__ bool wait_counter(const unsigned *ctr, unsigned targe
 }
 
 // A team is a fixed set of co-resident workgroups that cooperate on one
-// state.  Its barrier counts arrivals on monotonically increasing counters:
-// workgroups are split into groups of at most TEAM_GROUP, each group has its
-// own counter on its own cache line, and the last arrival of a group bumps
-// the top counter; the e-th barrier completes when the top counter reaches
-// e * (number of groups).  Counter block layout (words): top at 0, group g at
-// 32 * (1 + g); team_counter_words() gives its size.
-constexpr int TEAM_GROUP = 32;
+// state.  Its barrier is two-level and follows the chip's cache hierarchy:
+// the workgroups of the team that sit on the same XCD (read from the
+// hardware XCC_ID register when the launch starts) count their arrivals on
+// that XCD's counter; the last arrival of each XCD writes the XCD's L2 back
+// (agent-scope release) and, if the team spans several XCDs, meets the other
+// XCDs' last arrivals on the top counter; it then raises the XCD's
+// generation word, which the other workgroups of the XCD poll.  Every
+// workgroup ends with an agent-scope acquire.  Counters are monotone (the
+// e-th barrier waits for e * count), polled with relaxed agent-scope loads,
+// and every wait is bounded.  Counter block (words, one cache line each):
+// top at 0, arrivals of XCD x at 32*(1+x), generation of XCD x at 32*(9+x),
+// registrations of XCD x at 32*(17+x), set-up arrivals at 32*25.
+constexpr int TEAM_CTR_WORDS = 32 * 26;
 
-__host__ __device__ inline int team_groups(int size) { return (size + TEAM_GROUP - 1) / TEAM_GROUP; }
-__host__ __device__ inline int team_counter_words(int size) { return 32 * (1 + team_groups(size)); }
+__host__ __device__ inline int team_counter_words(int) { return TEAM_CTR_WORDS; }
+
+__device__ __forceinline__ int xcc_id() {
+    // s_getreg_b32 hwreg(HW_REG_XCC_ID, 0, 16)
+    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((16 - 1) << 11)) & 7;
+}
 
 struct Team {
     unsigned *ctr;    // counter block (zeroed before the launch)
@@ -177,7 +187,40 @@ struct Team {
     int size;         // workgroups in the team
     int rank;         // this workgroup's index in the team
     unsigned epoch;   // barriers passed so far (identical in all threads)
+    int xcc;          // this workgroup's XCD
+    int gx;           // workgroups of this team on that XCD
+    int nx;           // XCDs the team spans
+    int rpar;         // reduction slot set used by the next team_reduce (alternates)
 };
+
+// Must be called once by every workgroup of the team before any team_sync.
+__device__ __forceinline__ bool team_setup(Team &tm) {
+    __shared__ int s_gx, s_nx, s_ok;
+    tm.xcc = xcc_id();
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        int gx = 1, nx = 1;
+        if (tm.size > 1) {
+            __hip_atomic_fetch_add(tm.ctr + 32 * (17 + tm.xcc), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(tm.ctr + 32 * 25, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            ok = wait_counter(tm.ctr + 32 * 25, (unsigned)tm.size, tm.ctl);
+            nx = 0;
+            for (int x = 0; x < 8; ++x) nx += ld_relaxed(tm.ctr + 32 * (17 + x)) > 0u;
+            gx = (int)ld_relaxed(tm.ctr + 32 * (17 + tm.xcc));
+        }
+        s_gx = gx;
+        s_nx = nx;
+        s_ok = ok;
+    }
+    __syncthreads();
+    tm.gx = s_gx;
+    tm.nx = s_nx;
+    tm.epoch = 0;
+    tm.rpar = 0;
+    const bool ok = s_ok != 0;
+    __syncthreads();
+    return ok;
+}
 
 // Team barrier with agent-scope release/acquire ordering.  Returns false if
 // the launch was aborted (every caller then unwinds).  All threads of all
@@ -185,25 +228,24 @@ struct Team {
 __device__ __forceinline__ bool team_sync(Team &tm) {
     __shared__ int s_ok;
     tm.epoch += 1;
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached L2
     __syncthreads();
     if (threadIdx.x == 0) {
         bool ok = true;
         if (tm.size > 1) {
-            const int ng = team_groups(tm.size);
-            unsigned target;
-            if (ng == 1) {
-                __hip_atomic_fetch_add(tm.ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                target = tm.epoch * (unsigned)tm.size;
+            const unsigned old = __hip_atomic_fetch_add(tm.ctr + 32 * (1 + tm.xcc), 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            if (old + 1u == tm.epoch * (unsigned)tm.gx) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // write this XCD's L2 back
+                if (tm.nx > 1) {
+                    __hip_atomic_fetch_add(tm.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = wait_counter(tm.ctr, tm.epoch * (unsigned)tm.nx, tm.ctl);
+                }
+                __hip_atomic_store(tm.ctr + 32 * (9 + tm.xcc), tm.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                const int g = tm.rank / TEAM_GROUP;
-                const unsigned gsize = (unsigned)min(TEAM_GROUP, tm.size - g * TEAM_GROUP);
-                const unsigned old = __hip_atomic_fetch_add(tm.ctr + 32 * (1 + g), 1u, __ATOMIC_ACQ_REL,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
-                if (old + 1u == tm.epoch * gsize)
-                    __hip_atomic_fetch_add(tm.ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                target = tm.epoch * (unsigned)ng;
+                ok = wait_counter(tm.ctr + 32 * (9 + tm.xcc), tm.epoch, tm.ctl);
             }
-            ok = wait_counter(tm.ctr, target, tm.ctl);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         s_ok = ok && !__hip_atomic_load(&tm.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -211,23 +253,25 @@ __device__ __forceinline__ bool team_sync(Team &tm) {
     return s_ok != 0;
 }
 
-// Deterministic team all-reduce: every workgroup writes its partial to
-// buf[rank]; after the barrier every workgroup sums (or maxes) buf[0..size)
-// in the same fixed order, so all of them hold bit-identical results.
+// Deterministic team all-reduce: every workgroup writes its partial to its
+// slot; after the barrier every workgroup sums (or maxes) the slots in the
+// same fixed order, so all of them hold bit-identical results.  `base` holds
+// two sets of `size` slots; consecutive reductions alternate between them so
+// that a fast workgroup never overwrites a slot a slow one is still reading.
 template <bool MAX>
-__device__ __forceinline__ bool team_reduce(Team &tm, double part, double *buf, double &out,
-                                            double *lds) {
+__device__ __forceinline__ bool team_reduce(Team &tm, double part, double *base, double &out, double *lds) {
+    double *buf = base + tm.rpar * tm.size;
+    tm.rpar ^= 1;
     part = block_reduce<MAX>(part, lds);
     if (threadIdx.x == 0) buf[tm.rank] = part;
     if (!team_sync(tm)) return false;
-    double v = MAX ? 0.0 : 0.0;
     if (threadIdx.x < WAVE) {
-        double acc = MAX ? 0.0 : 0.0;
+        double acc = 0.0;
         for (int j = threadIdx.x; j < tm.size; j += WAVE) {
-            double b = buf[j];
+            const double b = buf[j];
             acc = MAX ? fmax(acc, b) : acc + b;
         }
-        v = MAX ? wave_max(acc) : wave_sum(acc);
+        const double v = MAX ? wave_max(acc) : wave_sum(acc);
         if (threadIdx.x == 0) lds[0] = v;
     }
     __syncthreads();

@@ -95,7 +95,7 @@ struct pr_problem {
     std::vector<Prob> P;
     std::vector<Buf> allocs;
     // synchronous workspace (single problem)
-    double *v = nullptr, *w = nullptr, *tmp = nullptr, *wn = nullptr;
+    double *v = nullptr, *w = nullptr, *tmp = nullptr, *wn = nullptr, *d0 = nullptr, *d1 = nullptr;
     double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *cg_q = nullptr, *red = nullptr;
     double *inv_tab = nullptr;        // 1D Thomas factors, padded
     unsigned *ctr = nullptr;          // team barrier counters
@@ -349,6 +349,9 @@ static SweepArgs sweep_args(pr_problem *h, const Prob &P, double *lam) {
     a.npts = P.npts;
     a.kguard = -1;
     a.delta = h->dscal;
+    a.incr = P.cfg.coarse_increment ? 1 : 0;
+    a.d0 = h->d0;
+    a.d1 = h->d1;
     a.cg_iters = h->iscal;
     a.n = P.n;
     a.s = P.s;
@@ -402,6 +405,8 @@ static int alloc_sync(pr_problem *h) {
         if ((rc = alloc_t(h, &h->cg_p0, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_p1, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_q, P.npts))) return rc;
+        if ((rc = alloc_t(h, &h->d0, P.npts))) return rc;
+        if ((rc = alloc_t(h, &h->d1, P.npts))) return rc;
     }
     return PR_OK;
 }

@@ -27,6 +27,8 @@ struct SweepArgs {
     int i0, i1;         // slices to sweep, inclusive
     int kguard;         // slice whose coarse input is known unchanged (-1: none)
     int init;           // 1: initial coarse sweep
+    int incr;           // 1: coarse solves act on the change of their input
+    double *d0, *d1;    // [npts] each: changes of consecutive slices (increment mode)
     double *delta;      // max-norm change (bit pattern max, zeroed by the host)
     unsigned long long *cg_iters;   // accumulated CG iterations (2D/3D)
     // 1D
@@ -55,6 +57,11 @@ __global__ __launch_bounds__(64) void k_sweep_1d(SweepArgs a) {
         x[e] = p < n ? a.lam[(a.i0 - 1) * a.npts + p] : 0.0;
     }
     double dmax = 0.0;
+    const bool incr = a.incr && !a.init;
+    if (incr) {
+#pragma unroll
+        for (int e = 0; e < R; ++e) x[e] = 0.0;   // the first slice's input is unchanged
+    }
     for (int i = a.i0; i <= a.i1; ++i) {
         double *li = a.lam + i * a.npts;
         double *wi = a.w + i * a.npts;
@@ -63,68 +70,117 @@ __global__ __launch_bounds__(64) void k_sweep_1d(SweepArgs a) {
         const bool skip = (i == a.kguard);
 #pragma unroll
         for (int e = 0; e < R; ++e) wnew[e] = x[e];
-        if (!skip) thomas_wave<R>(wnew, inv, n, a.s);
+        if (!skip) thomas_wave<R>(wnew, inv, n, a.s);   // G(input) or G(change of input)
 #pragma unroll
         for (int e = 0; e < R; ++e) {
             const int p = lane * R + e;
-            double lnew = 0.0;
+            double nx = 0.0;
             if (p < n) {
                 if (a.init) {
-                    lnew = wnew[e];
-                    wi[p] = lnew;
+                    nx = wnew[e];
+                    wi[p] = nx;
+                    li[p] = nx;
+                } else if (incr) {
+                    const double ln = vi[p] + (skip ? 0.0 : wnew[e]);
+                    nx = ln - li[p];                 // change of this slice = next input change
+                    dmax = fmax(dmax, fabs(nx));
+                    li[p] = ln;
                 } else {
                     const double wold = wi[p];
                     const double wv = skip ? wold : wnew[e];
-                    lnew = vi[p] + (wv - wold);
+                    const double lnew = vi[p] + (wv - wold);
                     dmax = fmax(dmax, fabs(lnew - li[p]));
                     wi[p] = wv;
+                    li[p] = lnew;
+                    nx = lnew;
                 }
-                li[p] = lnew;
             }
-            x[e] = lnew;
+            x[e] = nx;
         }
     }
     dmax = wave_max(dmax);
     if (lane == 0 && !a.init) atomic_max_nonneg(a.delta, dmax);
 }
 
-// Cooperative launch: the whole grid is one team.
-__global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
-    Team tm{a.ctr, a.ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
-    const ChunkRange cr = team_chunks(a.g, tm.rank, tm.size);
+// Sequential coarse sweep of slices i0..i1 of one problem by a team, with the
+// fused correction and change norm (shared by the synchronous and the batched
+// drivers).  kguard: slice whose coarse input is unchanged (skipped); init:
+// initial sweep lambda_i = w_i = G(lambda_{i-1}).  Increment mode: the solve
+// for slice i acts on the change d_{i-1} of its input (the previous slice's
+// change, produced by its correction), to an absolute residual tol*||input||.
+struct SweepBufs {
+    double *lam;
+    const double *v;
+    double *w, *wn, *d0, *d1;
+};
+
+__device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol, int maxit, long long npts,
+                                  int i0, int i1, int kguard, bool init, bool incr, const SweepBufs &B,
+                                  const CGWork &wk, double &dmax, unsigned long long &its, double *lds) {
+    const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
     const int w = wave_id();
-    double dmax = 0.0;
-    unsigned long long its = 0;
-    for (int i = a.i0; i <= a.i1; ++i) {
-        const double *b = a.lam + (long long)(i - 1) * a.npts;
-        double *li = a.lam + (long long)i * a.npts;
-        double *wi = a.w + (long long)i * a.npts;
-        const double *vi = a.v + (long long)i * a.npts;
-        const bool skip = (i == a.kguard);
+    const int nw = nwaves();
+    incr = incr && !init;
+    double *dprev = B.d0, *dnext = B.d1;
+    double nrm_prev = 0.0;
+    for (int i = i0; i <= i1; ++i) {
+        const bool skip = (!init && i == kguard);
+        double *li = B.lam + (long long)i * npts;
+        double *wi = B.w + (long long)i * npts;
+        const double *vi = B.v + (long long)i * npts;
         if (!skip) {
-            const int it = cg_team(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, a.wn, a.wk);
-            if (it < 0) return;
+            const int it = incr ? cg_team(tm, g, s, tol, maxit, dprev, B.wn, wk, tol * tol * nrm_prev)
+                                : cg_team(tm, g, s, tol, maxit, B.lam + (long long)(i - 1) * npts, B.wn, wk);
+            if (it < 0) return false;
             its += (unsigned long long)it;
         }
-        for (long long c = cr.begin + w; c < cr.end; c += nwaves()) {
-            const Point p = chunk_point(a.g, c);
+        double nrm = 0.0;
+        for (long long c = cr.begin + w; c < cr.end; c += nw) {
+            const Point p = chunk_point(g, c);
             if (!p.valid) continue;
-            if (a.init) {
-                const double wv = a.wn[p.idx];
+            if (init) {
+                const double wv = B.wn[p.idx];
                 li[p.idx] = wv;
                 wi[p.idx] = wv;
+            } else if (incr) {
+                const double ln = vi[p.idx] + (skip ? 0.0 : B.wn[p.idx]);
+                const double d = ln - li[p.idx];
+                dmax = fmax(dmax, fabs(d));
+                dnext[p.idx] = d;
+                nrm = __builtin_fma(ln, ln, nrm);
+                li[p.idx] = ln;
             } else {
                 const double wold = wi[p.idx];
-                const double wv = skip ? wold : a.wn[p.idx];
+                const double wv = skip ? wold : B.wn[p.idx];
                 const double lnew = vi[p.idx] + (wv - wold);
                 dmax = fmax(dmax, fabs(lnew - li[p.idx]));
                 li[p.idx] = lnew;
                 wi[p.idx] = wv;
             }
         }
-        if (!team_sync(tm)) return;
+        if (incr) {
+            if (!team_reduce<false>(tm, nrm, wk.red, nrm_prev, lds)) return false;
+            double *t = dprev;
+            dprev = dnext;
+            dnext = t;
+        } else if (!team_sync(tm)) {
+            return false;
+        }
     }
+    return true;
+}
+
+// Cooperative launch: the whole grid is one team.
+__global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
+    Team tm{a.ctr, a.ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
+    if (!team_setup(tm)) return;
     __shared__ double lds[MAX_WAVES];
+    double dmax = 0.0;
+    unsigned long long its = 0;
+    const SweepBufs B{a.lam, a.v, a.w, a.wn, a.d0, a.d1};
+    if (!team_coarse_sweep(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
+                           a.incr != 0, B, a.wk, dmax, its, lds))
+        return;
     dmax = block_reduce<true>(dmax, lds);
     if (threadIdx.x == 0) {
         if (!a.init) atomic_max_nonneg(a.delta, dmax);
@@ -140,6 +196,7 @@ __global__ __launch_bounds__(1024) void k_coarse_cg_batch(const double *src, dou
                                                            int maxit, CGWork wk, unsigned *ctr,
                                                            Control *ctl, unsigned long long *cg_iters) {
     Team tm{ctr, ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
+    if (!team_setup(tm)) return;
     unsigned long long its = 0;
     for (int c = 0; c < count; ++c) {
         const int it = cg_team(tm, g, s, tol, maxit, src + c * npts, dst + c * npts, wk);
