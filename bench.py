@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+ASYNC_DEPTH = 4         # fine steps per pass inside the persistent asynchronous kernel (2D)
 
 
 def parse():
@@ -33,6 +34,8 @@ def parse():
     ap.add_argument("--cpu-sample-slices", type=int, default=64)
     ap.add_argument("--only", choices=["both", "sync", "async"], default="both",
                     help="restrict the step to one driver (profiling runs)")
+    ap.add_argument("--no-increment", action="store_true",
+                    help="skip the untimed runs with coarse solves on input changes")
     return ap.parse_args()
 
 
@@ -52,6 +55,12 @@ def cpu_baseline(p, nslices_sample):
             "sample": f"oracle fine propagator F, {nslices_sample} of the 64 slices "
                       f"({nslices_sample}x{d.m} explicit-Euler steps on the 1024^2 grid), "
                       f"{dt:.1f} s, single-threaded NumPy"}
+
+
+def fine_kernel_name(info):
+    if info.sliding:
+        return f"k_fine2d_sw<{info.xpts},{info.tb_depth}> (rows {info.tile_rows})"
+    return f"k_fine2d<{info.xpts},{info.tile_rows},{info.tb_depth}>"
 
 
 def main():
@@ -107,6 +116,29 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
+    # ---- outside the timed region: the fine sweep alone (every slice, m steps)
+    #      and both drivers with coarse solves on input changes (linear G)
+    xs = lam_s[:N].clone()
+    ys = torch.empty_like(xs)
+    prob.apply_fine(xs, ys, N, m)
+    t1 = time.perf_counter()
+    for _ in range(5):
+        prob.apply_fine(xs, ys, N, m)
+    sweep_ms = (time.perf_counter() - t1) / 5 * 1e3
+    fine_sweep = {"kernel": fine_kernel_name(info), "ms": sweep_ms,
+                  "glups": N * m * npts / (sweep_ms * 1e-3) / 1e9,
+                  "hbm_frac": N * -(-m // info.tb_depth) * 16.0 * npts / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    incr = {}
+    if not args.no_increment:
+        pi = pr.Problem(pr.config_of(p, eps=1e-10, coarse_increment=1))
+        pi.set_async_options(mode=pr.PR_ASYNC_FREE, time_limit_s=200.0)
+        lam_i = torch.empty_like(lam_s)
+        for drv in (("sync", "async") if args.only == "both" else (args.only,)):
+            st = pr.Stats(N, N + 1) if drv == "sync" else pr.Stats(N)
+            (pi.solve_sync if drv == "sync" else pi.solve_async)(u0, lam_i, st)
+            incr[drv] = {"ms": st.wall_ms, "iters": st.iters, "cg_iters": st.cg_iters,
+                         "rel_err_vs_serial_fine": (lam_i - ser).abs().max().item() / ser.abs().max().item()}
+
     sref = ser.abs().max().item()
     err_s = (lam_s - ser).abs().max().item() / sref if rec["sync"] else None
     err_a = (lam_a - ser).abs().max().item() / sref if rec["async"] else None
@@ -115,21 +147,25 @@ def main():
     value = lups / wall / 1e9
 
     # ---- roofline objects (algorithmic bytes per launch / live event durations)
+    # Algorithmic bytes per point: F pass 16 (read + write the state); CG
+    # iteration 64 (phase A reads r, p_old, writes p; phase B reads p, x, r,
+    # writes x, r); CG set-up 24 (read b, write x, r); correction 48 (read v,
+    # w_new, w_old, lambda_old, write lambda, w).
     D = info.tb_depth
     passes = -(-m // D)
+    fine_kernel = fine_kernel_name(info)
     rl = {}
     if rec["sync"]:
         s = rec["sync"]
         f_ms = sum(x["fine_ms"] for x in s)
-        f_bytes = sum(x["fine_lups"] for x in s) / m * passes * 16.0   # 16 B/pt per pass
+        f_bytes = sum(x["fine_lups"] for x in s) / m * passes * 16.0
         f_launches = sum(x["iters"] for x in s) * passes
-        rl["fine"] = {"kernel": f"k_fine2d<2,{info.tile_rows},{D}>", "bound": "hbm",
+        rl["fine"] = {"kernel": fine_kernel, "bound": "hbm",
                       "achieved": f_bytes / (f_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "launches": f_launches, "avg_launch_ms": f_ms / f_launches,
                       "glups": sum(x["fine_lups"] for x in s) / (f_ms * 1e-3) / 1e9}
         c_ms = sum(x["coarse_ms"] for x in s)
-        # CG: 80 B/pt per iteration, 24 B/pt per solve set-up; correction 48 B/pt per slice
-        c_bytes = sum(x["cg_iters"] * 80.0 * npts + x["g_solves"] * 24.0 * npts
+        c_bytes = sum(x["cg_iters"] * 64.0 * npts + x["g_solves"] * 24.0 * npts
                       + (x["g_solves"] + x["g_skipped"]) * 48.0 * npts for x in s)
         c_launches = sum(x["iters"] + 1 for x in s)
         rl["sweep"] = {"kernel": "k_sweep_cg", "bound": "hbm", "achieved": c_bytes / (c_ms * 1e-3) / 1e9,
@@ -138,13 +174,15 @@ def main():
     if rec["async"]:
         a = rec["async"]
         k_ms = sum(x["kernel_ms"] for x in a)
+        a_passes = -(-m // ASYNC_DEPTH)
         a_bytes = 0.0
         for x in a:
             upd = x["kernel_updates"]
             solves = x["g_solves"] - N          # minus the initial coarse sweep
-            a_bytes += (upd * passes * 16.0 + x["kernel_cg_iters"] * 80.0 + solves * (24.0 + 16.0)
-                        + upd * 40.0) * npts
-        rl["async"] = {"kernel": "k_async<2,2,16,8>", "bound": "hbm",
+            # per update: F passes, predecessor copy 16, correction + next slot 48
+            a_bytes += (upd * (a_passes * 16.0 + 16.0 + 48.0) + x["kernel_cg_iters"] * 64.0
+                        + solves * 24.0) * npts
+        rl["async"] = {"kernel": f"k_async<2,2,128,{ASYNC_DEPTH}>", "bound": "hbm",
                        "achieved": a_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "launches": len(a), "avg_launch_ms": k_ms / len(a)}
     for r in rl.values():
@@ -171,6 +209,8 @@ def main():
                    "parallelism": "time slices on one GPU (persistent teams for async)"},
         "roofline": roofline,
         "roofline_fine": rl.get("fine"),
+        "fine_sweep": fine_sweep,
+        "time_to_tol_ms_increment": incr,
         "roofline_kernels": rl,
         "time_to_tol_ms": {
             "sync": float(np.median([x["wall_ms"] for x in rec["sync"]])) if rec["sync"] else None,

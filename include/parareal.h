@@ -68,12 +68,17 @@ typedef struct pr_config {
     int    cg_maxit;     /* <= 0 means 10*n + 100 */
     double eps;          /* stop when ||lambda^k - lambda^{k-1}||_inf < eps; <= 0: run kmax */
     int    kmax;         /* iteration cap; <= 0 or > N means N (finite termination) */
-    int    tb_depth;     /* fine steps per HBM pass (temporal block depth); 0 = tuned */
-    int    tile_rows;    /* rows per register strip of the fine kernel; 0 = tuned */
+    int    tb_depth;     /* fine steps per HBM pass (temporal block depth); 0 = default */
+    int    tile_rows;    /* 2D/3D fine kernel: rows a wave owns; below 96 a register strip
+                            (rows held at once), from 96 on a sliding window (rows marched
+                            per segment, two rows per time level held); 0 = default */
     int    coarse_increment; /* 0: G(new) - G(old) as written in eq. (pr) / Algorithm 2;
                                 1: G applied to the change new - old (G is linear, Section 3.1),
                                 CG from 0 to an absolute residual tol*||new||; an unchanged input
                                 gives exactly 0.  Fewer CG iterations, same fixed point. */
+    int    fine_xpts;    /* x points per lane of the fine kernel (2D/3D); 0 = default.  The
+                            first shape matching every nonzero (tb_depth, tile_rows,
+                            fine_xpts) is used; none matching is PR_EINVAL. */
 } pr_config;
 
 /* Derived discretisation of one problem (read-only view). */
@@ -85,6 +90,7 @@ typedef struct pr_info {
     long long npts;      /* n^dim */
     long long offset;    /* index of this problem's lambda_0[0] in a concatenated iterate */
     int    tb_depth, tile_rows;   /* fine-kernel shape in use */
+    int    xpts, sliding;         /* its x points per lane; 1 for a sliding window */
 } pr_info;
 
 typedef struct pr_stats {
@@ -181,12 +187,14 @@ int  pr_fine_shape_count(int dim);
  * `reps` timed runs each, and selects the fastest.  Results are cached per
  * process and, if the environment variable PR_TUNE_CACHE names a file, in
  * that file.  Outputs (may be NULL): the chosen depth / rows and its time. */
-int  pr_autotune(pr_problem *h, int problem, int reps, int *tb_depth, int *tile_rows, double *best_ms);
+int  pr_autotune(pr_problem *h, int problem, int reps, int *tb_depth, int *tile_rows, int *xpts,
+                 double *best_ms);
 /* Batched handles: capture one iteration of the whole batch as a hipGraph
  * and replay it (enable = 1, the default) or launch it directly (0). */
 int  pr_set_graph(pr_problem *h, int enable);
-int  pr_fine_shape_get(int dim, int index, int *tb_depth, int *tile_rows, int *xpts);
-int  pr_set_fine_shape(pr_problem *h, int problem, int tb_depth, int tile_rows);
+int  pr_fine_shape_get(int dim, int index, int *tb_depth, int *tile_rows, int *xpts, int *sliding);
+/* first shape matching every given (> 0) parameter; PR_EINVAL if none */
+int  pr_set_fine_shape(pr_problem *h, int problem, int tb_depth, int tile_rows, int xpts);
 
 #ifdef __cplusplus
 }

@@ -39,6 +39,7 @@ class pr_config(ctypes.Structure):
         ("coarse", ctypes.c_int), ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
         ("eps", ctypes.c_double), ("kmax", ctypes.c_int), ("tb_depth", ctypes.c_int),
         ("tile_rows", ctypes.c_int), ("coarse_increment", ctypes.c_int),
+        ("fine_xpts", ctypes.c_int),
     ]
 
 
@@ -48,6 +49,7 @@ class pr_info(ctypes.Structure):
         ("h", ctypes.c_double), ("r", ctypes.c_double), ("s", ctypes.c_double),
         ("npts", ctypes.c_longlong), ("offset", ctypes.c_longlong),
         ("tb_depth", ctypes.c_int), ("tile_rows", ctypes.c_int),
+        ("xpts", ctypes.c_int), ("sliding", ctypes.c_int),
     ]
 
 
@@ -107,10 +109,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pr_apply_fine.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int]
     lib.pr_apply_coarse.argtypes = [P, P, P, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
     lib.pr_fine_shape_count.argtypes = [ctypes.c_int]
-    lib.pr_fine_shape_get.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3
-    lib.pr_set_fine_shape.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.pr_fine_shape_get.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4
+    lib.pr_set_fine_shape.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.pr_autotune.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
-                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_double)]
     lib.pr_set_graph.argtypes = [P, ctypes.c_int]
     _lib = lib
     return lib
@@ -146,9 +149,9 @@ def _ptr(x) -> int:
 
 def make_config(dim, n, nu, T, nslices, dt_nominal, coarse=PR_COARSE_AUTO, cg_tol=1e-12,
                 cg_maxit=0, eps=1e-10, kmax=0, tb_depth=0, tile_rows=0,
-                coarse_increment=0) -> pr_config:
+                coarse_increment=0, fine_xpts=0) -> pr_config:
     return pr_config(dim, n, nu, T, nslices, dt_nominal, coarse, cg_tol, cg_maxit, eps, kmax,
-                     tb_depth, tile_rows, coarse_increment)
+                     tb_depth, tile_rows, coarse_increment, fine_xpts)
 
 
 def config_of(problem, **over) -> pr_config:
@@ -273,14 +276,15 @@ class Problem:
         _check(self.lib.pr_apply_coarse(self.h, _ptr(x), _ptr(y), count, ctypes.byref(it)))
         return it.value
 
-    def set_fine_shape(self, tb_depth: int, tile_rows: int, problem: int = 0):
-        _check(self.lib.pr_set_fine_shape(self.h, problem, tb_depth, tile_rows))
+    def set_fine_shape(self, tb_depth: int, tile_rows: int, xpts: int = 0, problem: int = 0):
+        _check(self.lib.pr_set_fine_shape(self.h, problem, tb_depth, tile_rows, xpts))
 
     def autotune(self, problem: int = 0, reps: int = 3):
-        """Runs the library's autotuner; returns (tb_depth, tile_rows, best_ms)."""
-        d, r, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
-        _check(self.lib.pr_autotune(self.h, problem, reps, ctypes.byref(d), ctypes.byref(r), ctypes.byref(ms)))
-        return d.value, r.value, ms.value
+        """Runs the library's autotuner; returns (tb_depth, tile_rows, xpts, best_ms)."""
+        d, r, x, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(self.lib.pr_autotune(self.h, problem, reps, ctypes.byref(d), ctypes.byref(r), ctypes.byref(x),
+                                    ctypes.byref(ms)))
+        return d.value, r.value, x.value, ms.value
 
     def set_graph(self, enable: bool):
         _check(self.lib.pr_set_graph(self.h, 1 if enable else 0))
@@ -294,12 +298,13 @@ class Problem:
 
 
 def fine_shapes(dim: int):
+    """[(tb_depth, tile_rows, xpts, sliding)] of every fine-kernel shape."""
     lib = load_library()
     out = []
     for i in range(lib.pr_fine_shape_count(dim)):
-        d, r, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(lib.pr_fine_shape_get(dim, i, ctypes.byref(d), ctypes.byref(r), ctypes.byref(x)))
-        out.append((d.value, r.value, x.value))
+        d, r, x, sw = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib.pr_fine_shape_get(dim, i, ctypes.byref(d), ctypes.byref(r), ctypes.byref(x), ctypes.byref(sw)))
+        out.append((d.value, r.value, x.value, sw.value))
     return out
 
 

@@ -76,8 +76,9 @@ struct AsyncWork {
     unsigned *tctr = nullptr;
     long long *tbc = nullptr;
     double *tred = nullptr;
-    double *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr, *cgq = nullptr;
+    double *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr;
     unsigned long long *counters = nullptr;
+    void *args = nullptr;   // the launch's AsyncArgs, in device memory
     // the configuration these buffers were sized for
     int R = 0, L = 0, nteams = 0, grid = 0, maxtsz = 0, withS = 0;
 };
@@ -103,7 +104,7 @@ struct AsyncArgs {
     unsigned *tctr;          // [nteams * 16]
     long long *tbc;          // [nteams * 16] leader broadcasts
     double *tred;            // [nteams * 2 * maxtsz]
-    double *cgr, *cgp0, *cgp1, *cgq;   // [nteams * npts]
+    double *cgr, *cgp0, *cgp1;   // [nteams * npts]
     Control *ctl;
     unsigned long long *counters;   // cg iterations, coarse solves, skipped solves, copy retries, idle rounds
     // fine-kernel geometry
@@ -120,13 +121,17 @@ __device__ __forceinline__ bool team_bcast(Team &tm, long long *slots, long long
     const int par = (tm.epoch + 1) & 1;
     if (tm.rank == 0 && threadIdx.x == 0) {
         v[7] = __hip_atomic_load(&tm.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
         for (int j = 0; j < 8; ++j) slots[par * 8 + j] = v[j];
     }
     if (!team_sync(tm)) return false;
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
+#pragma unroll
         for (int j = 0; j < 8; ++j) s_v[j] = slots[par * 8 + j];
+    }
     __syncthreads();
-    for (int j = 0; j < 8; ++j) v[j] = s_v[j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = uniform(s_v[j]);
     __syncthreads();
     return v[7] == 0;
 }
@@ -219,8 +224,17 @@ __device__ bool team_fine(Team &tm, const AsyncArgs &a, const double *src, doubl
             if constexpr (DIM == 2) {
                 const int st = min(D, a.m - p * D);
                 const int total = a.nsx * a.nsy;
-                for (int sidx = wid; sidx < total; sidx += waves)
-                    fine2d_strip<XP, RR, D>(cur, tgt, a.n, a.r, st, sidx / a.nsy, sidx % a.nsy);
+                for (int sidx = wid; sidx < total; sidx += waves) {
+                    if constexpr (RR >= SW_MIN_ROWS) {
+                        const int ya = (sidx % a.nsy) * RR;
+                        // two rows in flight: this persistent kernel's occupancy is set by
+                        // its registers, and CG, not F, dominates its time
+                        fine2d_sw<XP, D, 2>(cur, tgt, a.n, a.r, st, sidx / a.nsy, ya, min(a.n, ya + RR),
+                                         (sidx % a.nsy) & 1);
+                    } else {
+                        fine2d_strip<XP, RR, D>(cur, tgt, a.n, a.r, st, sidx / a.nsy, sidx % a.nsy);
+                    }
+                }
             } else {
                 const int total = a.nsx * a.nsy * a.nsz;
                 for (int sidx = wid; sidx < total; sidx += waves) {
@@ -263,7 +277,9 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
         }
         return team_sync(tm) ? 0 : -1;
     } else {
-        const int it = cg_team(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
+        // one chunk per loop trip: the persistent kernel also holds the fine
+        // propagator and the slice state, so registers decide its occupancy
+        const int it = cg_team_dim<DIM, 1>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
         if (it < 0) return -1;
         return team_sync(tm) ? it : -1;
     }
@@ -271,8 +287,12 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
 
 enum { ACT_IDLE = 0, ACT_UPDATE = 1, ACT_DONE = 2 };
 
+// The arguments live in device memory: read through a uniform pointer they
+// stay in scalar registers, where a by-value struct passed on by reference
+// would be copied to scratch.
 template <int DIM, int XP, int RR, int D>
-__global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ ap) {
+    const AsyncArgs &a = *ap;
     const int team = a.team_of[blockIdx.x];
     if (team < 0) return;
     const int rank = a.rank_of[blockIdx.x];
@@ -280,7 +300,7 @@ __global__ __launch_bounds__(BLOCK) void k_async(AsyncArgs a) {
     if (!team_setup(tm)) return;
     long long *bc = a.tbc + team * 16;
     CGWork wk{a.cgr + (long long)team * a.npts, a.cgp0 + (long long)team * a.npts,
-              a.cgp1 + (long long)team * a.npts, a.cgq + (long long)team * a.npts,
+              a.cgp1 + (long long)team * a.npts,
               a.tred + (long long)team * 2 * a.maxtsz};
     __shared__ double lds[MAX_WAVES];
     const bool leader = (rank == 0 && threadIdx.x == 0);

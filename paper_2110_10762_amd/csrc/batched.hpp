@@ -54,7 +54,7 @@ struct BatchArgs {
     unsigned *tctr;
     long long *tbc;
     double *tred;
-    double *wn, *cgr, *cgp0, *cgp1, *cgq, *d0, *d1;   // [nteams][maxnpts]
+    double *wn, *cgr, *cgp0, *cgp1, *d0, *d1;   // [nteams][maxnpts]
     long long maxnpts;
     const int *order;
     unsigned *queue;
@@ -84,6 +84,30 @@ __global__ __launch_bounds__(BLOCK) void k_bfine(const BProb *__restrict__ prob,
     fine2d_strip<XP, R, D>(src, target(pass), n, P.r, steps, strip / nsy, strip % nsy);
 }
 
+template <int XP, int D>
+__global__ __launch_bounds__(BLOCK) void k_bfine_sw(const BProb *__restrict__ prob, const BState *__restrict__ st,
+                                                    const int *__restrict__ unit_b, const int *__restrict__ unit_i,
+                                                    int nunits, int n, int nsx, int nsy, int ry, int pass,
+                                                    const double *lam, double *v, double *tmp, int nblk) {
+    const int L = xcd_remap(blockIdx.x, nblk);
+    if (L >= nblk) return;
+    const long long wv = (long long)L * WAVES_PER_BLOCK + wave_id();
+    const long long per = (long long)nsx * nsy;
+    const long long u = wv / per;
+    if (u >= nunits) return;
+    const int strip = (int)(wv - u * per);
+    const int b = unit_b[u], i = unit_i[u];
+    const BProb &P = prob[b];
+    const BState &S = st[b];
+    if (!S.active || S.k < 1 || i < S.k || pass >= P.passes) return;
+    const int steps = min(D, P.m - pass * D);
+    const long long here = P.off_lam + (long long)i * P.npts;
+    auto target = [&](int p) { return ((P.passes - 1 - p) % 2 == 0) ? v + here : tmp + here; };
+    const double *src = pass == 0 ? lam + P.off_lam + (long long)(i - 1) * P.npts : target(pass - 1);
+    const int ya = (strip % nsy) * ry;
+    fine2d_sw<XP, D>(src, target(pass), n, P.r, steps, strip / nsy, ya, min(n, ya + ry), (strip % nsy) & 1);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_bsweep(BatchArgs a) {
     const int team = a.team_of[blockIdx.x];
     if (team < 0) return;
@@ -92,7 +116,7 @@ __global__ __launch_bounds__(BLOCK) void k_bsweep(BatchArgs a) {
     long long *bc = a.tbc + team * 16;
     double *wn = a.wn + team * a.maxnpts;
     CGWork wk{a.cgr + team * a.maxnpts, a.cgp0 + team * a.maxnpts, a.cgp1 + team * a.maxnpts,
-              a.cgq + team * a.maxnpts, a.tred + (long long)team * 2 * a.tsz};
+              a.tred + (long long)team * 2 * a.tsz};
     __shared__ double lds[MAX_WAVES];
     const bool leader = (tm.rank == 0 && threadIdx.x == 0);
     for (;;) {
@@ -106,7 +130,7 @@ __global__ __launch_bounds__(BLOCK) void k_bsweep(BatchArgs a) {
             if (!team_sync(tm)) return;
             if (threadIdx.x == 0) s_c = bc[par * 8];
             __syncthreads();
-            c[0] = s_c;
+            c[0] = uniform(s_c);
             __syncthreads();
         }
         if (c[0] >= a.B) break;
@@ -163,7 +187,7 @@ struct BatchWork {
     int *order = nullptr, *team_of = nullptr, *rank_of = nullptr;
     unsigned *tctr = nullptr, *queue = nullptr;
     long long *tbc = nullptr;
-    double *tred = nullptr, *wn = nullptr, *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr, *cgq = nullptr;
+    double *tred = nullptr, *wn = nullptr, *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr;
     double *d0 = nullptr, *d1 = nullptr;
     long long maxnpts = 0, total = 0;
     int nteams = 0, tsz = 0, grid = 0;

@@ -202,48 +202,136 @@ __device__ __forceinline__ double be_point(double yc, double nsum, double twod, 
 
 // ------------------------------------------------------------------ CG
 struct CGWork {
-    double *r, *p0, *p1, *q;   // [npts] each
-    double *red;               // [2 * team size] reduction slots
+    double *r, *p0, *p1;   // [npts] each
+    double *red;           // [2 * team size] reduction slots
 };
 
-// Solves (I - s h^2 L_h) x = b by CG with the team.  Returns the iteration
-// count, or -1 if the launch was aborted.  x and b must not alias.  All
-// lanes of a wave run every chunk (lanes past the row end carry zeros) so
-// that the lane shifts see the whole chunk.
+// A chunk point for the CG phases: its index (a state holds < 2^31 points)
+// and which neighbours exist.  A missing neighbour (outside the domain, or
+// any neighbour of a lane past the row end) is read at the point itself and
+// masked, so all loads can be issued unconditionally and early.  The edge
+// neighbour is the x-neighbour across the chunk border (lane 0: left, lane 63:
+// right); the other x-neighbours come by DPP.
+struct CPt {
+    int c;
+    unsigned m;   // bits: valid, up, down, front, back, edge
+};
+constexpr unsigned CP_VALID = 1, CP_UP = 2, CP_DN = 4, CP_FR = 8, CP_BK = 16, CP_EDGE = 32;
+
+__device__ __forceinline__ CPt cpt_at(const Geom &g, long long chunk) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const Point p = chunk_point(g, chunk);
+    CPt q;
+    q.c = (int)(p.valid ? p.idx : p.idx - p.x);
+    unsigned m = 0;
+    if (p.valid) {
+        m |= CP_VALID;
+        if (g.dim >= 2 && p.y > 0) m |= CP_UP;
+        if (g.dim >= 2 && p.y + 1 < g.n) m |= CP_DN;
+        if (g.dim == 3 && p.z > 0) m |= CP_FR;
+        if (g.dim == 3 && p.z + 1 < g.n) m |= CP_BK;
+        if ((lane == 0 && p.x > 0) || (lane == WAVE - 1 && p.x + 1 < g.n)) m |= CP_EDGE;
+    }
+    q.m = m;
+    return q;
+}
+
+// Loads the value of the point and of its neighbours: v[0] centre, v[1] up,
+// v[2] down, v[3] edge, v[4] front, v[5] back (DIM == 3).
+template <int DIM, typename Fn>
+__device__ __forceinline__ void cpt_load(const CPt &q, int n, Fn f, double (&v)[2 * DIM]) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    v[0] = f(q.c);
+    v[1] = f((q.m & CP_UP) ? q.c - n : q.c);
+    v[2] = f((q.m & CP_DN) ? q.c + n : q.c);
+    v[3] = f((q.m & CP_EDGE) ? (lane == 0 ? q.c - 1 : q.c + 1) : q.c);
+    if constexpr (DIM == 3) {
+        v[4] = f((q.m & CP_FR) ? q.c - n * n : q.c);
+        v[5] = f((q.m & CP_BK) ? q.c + n * n : q.c);
+    }
+}
+
+// (I - s h^2 L_h) applied at the point: centre value masked to 0 past the
+// row end, neighbour sum in the order of neighbour_sum.
+template <int DIM>
+__device__ __forceinline__ double cpt_apply(const CPt &q, const double (&v)[2 * DIM], double &center,
+                                            double twod, double s) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    center = (q.m & CP_VALID) ? v[0] : 0.0;
+    double xl = from_lower_lane(center);
+    double xr = from_upper_lane(center);
+    const double ve = (q.m & CP_EDGE) ? v[3] : 0.0;
+    if (lane == 0) xl = ve;
+    if (lane == WAVE - 1) xr = ve;
+    double s2 = ((q.m & CP_UP) ? v[1] : 0.0) + ((q.m & CP_DN) ? v[2] : 0.0);
+    if constexpr (DIM == 3) s2 = s2 + (((q.m & CP_FR) ? v[4] : 0.0) + ((q.m & CP_BK) ? v[5] : 0.0));
+    return be_point(center, s2 + (xl + xr), twod, s);
+}
+
+// Solves (I - s h^2 L_h) x = b by CG with the team (DIM = 2 or 3; U chunks
+// per wave and loop trip, whose loads are all issued before the first is
+// used: memory-level parallelism against register use).  Returns
+// the iteration count, or -1 if the launch was aborted.  x and b must not
+// alias.  All lanes of a wave run every chunk (lanes past the row end carry
+// zeros) so that the lane shifts see the whole chunk.
 //   abs_thresh2 < 0: x0 = b, stop at ||r||^2 <= tol^2 ||b||^2 (the coarse
 //                    propagator applied to a state);
 //   abs_thresh2 >= 0: x0 = 0, stop at ||r||^2 <= abs_thresh2 (applied to the
 //                    change of a state: a zero right-hand side returns 0).
-__device__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
-                       const double *__restrict__ b, double *__restrict__ x, const CGWork &wk,
-                       double abs_thresh2 = -1.0) {
+// Per iteration: phase A forms p = r + beta p_old (recomputed at the
+// neighbours from r and p_old), stores p and reduces <p, A p>; phase B
+// updates x and r, recomputing A p from the stored p (bit-identical to phase
+// A's value) instead of storing it: 64 B of HBM traffic per point.
+template <int DIM, int U>
+__device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int maxit,
+                           const double *__restrict__ b, double *__restrict__ x, const CGWork &wk,
+                           double abs_thresh2) {
+    constexpr int V = 2 * DIM;
     __shared__ double lds[MAX_WAVES];
-    const double twod = 2.0 * g.dim;
+    const double twod = 2.0 * DIM;
+    const int n = g.n;
     const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
     const int w = wave_id();
-    const int nw = nwaves();
+    const long long nw = nwaves();
     double *__restrict__ r = wk.r;
-    double *__restrict__ q = wk.q;
     const bool from_zero = abs_thresh2 >= 0.0;
 
     double rr_p = 0.0, bb_p = 0.0;
-    for (long long c = cr.begin + w; c < cr.end; c += nw) {
-        const Point p = chunk_point(g, c);
-        const double bc = p.valid ? b[p.idx] : 0.0;
-        if (from_zero) {                       // r = b, x = 0
-            if (p.valid) {
-                x[p.idx] = 0.0;
-                r[p.idx] = bc;
-                rr_p = __builtin_fma(bc, bc, rr_p);
+    for (long long c0 = cr.begin + w; c0 < cr.end; c0 += U * nw) {
+        CPt q[U];
+        bool act[U];
+        double v[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long c = c0 + u * nw;
+            act[u] = c < cr.end;
+            q[u] = cpt_at(g, act[u] ? c : c0);
+            if (from_zero) {
+                v[u][0] = b[q[u].c];
+            } else {
+                cpt_load<DIM>(q[u], n, [&](int j) { return b[j]; }, v[u]);
             }
-        } else {                               // r = b - A b, x = b
-            const double ns = neighbour_sum(g, p, bc, [&](long long j) { return b[j]; });
-            if (p.valid) {
-                const double rv = bc - be_point(bc, ns, twod, s);
-                x[p.idx] = bc;
-                r[p.idx] = rv;
-                rr_p = __builtin_fma(rv, rv, rr_p);
-                bb_p = __builtin_fma(bc, bc, bb_p);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool keep = act[u] && (q[u].m & CP_VALID);
+            if (from_zero) {                       // r = b, x = 0
+                const double bv = v[u][0];
+                if (keep) {
+                    x[q[u].c] = 0.0;
+                    r[q[u].c] = bv;
+                    rr_p = __builtin_fma(bv, bv, rr_p);
+                }
+            } else {                               // r = b - A b, x = b
+                double bv;
+                const double ab = cpt_apply<DIM>(q[u], v[u], bv, twod, s);
+                const double rv = bv - ab;
+                if (keep) {
+                    x[q[u].c] = bv;
+                    r[q[u].c] = rv;
+                    rr_p = __builtin_fma(rv, rv, rr_p);
+                    bb_p = __builtin_fma(bv, bv, bb_p);
+                }
             }
         }
     }
@@ -263,31 +351,58 @@ __device__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
     double *pcur = wk.p0;
     int it = 0;
     while (it < maxit && rr > thresh) {
-        // phase A: p = r + beta p_old (also at neighbours), q = A p, <p, q>
+        // phase A: p = r + beta p_old (also at the neighbours), <p, A p>
         double pq_p = 0.0;
-        for (long long c = cr.begin + w; c < cr.end; c += nw) {
-            const Point p = chunk_point(g, c);
-            auto pn = [&](long long j) { return __builtin_fma(beta, pold[j], r[j]); };
-            const double pc = p.valid ? pn(p.idx) : 0.0;
-            const double qv = be_point(pc, neighbour_sum(g, p, pc, pn), twod, s);
-            if (p.valid) {
-                pcur[p.idx] = pc;
-                q[p.idx] = qv;
-                pq_p = __builtin_fma(pc, qv, pq_p);
+        for (long long c0 = cr.begin + w; c0 < cr.end; c0 += U * nw) {
+            CPt q[U];
+            bool act[U];
+            double v[U][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long long c = c0 + u * nw;
+                act[u] = c < cr.end;
+                q[u] = cpt_at(g, act[u] ? c : c0);
+                cpt_load<DIM>(q[u], n, [&](int j) { return __builtin_fma(beta, pold[j], r[j]); }, v[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                double pv;
+                const double qv = cpt_apply<DIM>(q[u], v[u], pv, twod, s);
+                if (act[u] && (q[u].m & CP_VALID)) {
+                    pcur[q[u].c] = pv;
+                    pq_p = __builtin_fma(pv, qv, pq_p);
+                }
             }
         }
         double pq;
         if (!team_reduce<false>(tm, pq_p, wk.red, pq, lds)) return -1;
         const double alpha = rr / pq;
-        // phase B: x += alpha p, r -= alpha q, <r, r>
+        // phase B: x += alpha p, r -= alpha A p, <r, r>
         double rn_p = 0.0;
-        for (long long c = cr.begin + w; c < cr.end; c += nw) {
-            const Point p = chunk_point(g, c);
-            if (!p.valid) continue;
-            x[p.idx] = __builtin_fma(alpha, pcur[p.idx], x[p.idx]);
-            const double rv = __builtin_fma(-alpha, q[p.idx], r[p.idx]);
-            r[p.idx] = rv;
-            rn_p = __builtin_fma(rv, rv, rn_p);
+        for (long long c0 = cr.begin + w; c0 < cr.end; c0 += U * nw) {
+            CPt q[U];
+            bool act[U];
+            double v[U][V], xc[U], rc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long long c = c0 + u * nw;
+                act[u] = c < cr.end;
+                q[u] = cpt_at(g, act[u] ? c : c0);
+                cpt_load<DIM>(q[u], n, [&](int j) { return pcur[j]; }, v[u]);
+                xc[u] = x[q[u].c];
+                rc[u] = r[q[u].c];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                double pv;
+                const double qv = cpt_apply<DIM>(q[u], v[u], pv, twod, s);
+                if (act[u] && (q[u].m & CP_VALID)) {
+                    x[q[u].c] = __builtin_fma(alpha, pv, xc[u]);
+                    const double rv = __builtin_fma(-alpha, qv, rc[u]);
+                    r[q[u].c] = rv;
+                    rn_p = __builtin_fma(rv, rv, rn_p);
+                }
+            }
         }
         double rn;
         if (!team_reduce<false>(tm, rn_p, wk.red, rn, lds)) return -1;
@@ -298,6 +413,13 @@ __device__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
         ++it;
     }
     return it;
+}
+
+__device__ __forceinline__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
+                                       const double *__restrict__ b, double *__restrict__ x, const CGWork &wk,
+                                       double abs_thresh2 = -1.0) {
+    if (g.dim == 3) return cg_team_dim<3, 1>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+    return cg_team_dim<2, 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
 
 }  // namespace pr

@@ -26,17 +26,30 @@ __device__ __forceinline__ int wave_id() {
 // Whole-wave DPP row moves: wave_shr:1 moves data to the next higher lane
 // (lane l receives lane l-1), wave_shl:1 to the next lower lane.  Lanes
 // whose source is outside the wave receive 0.
+// (bound_ctrl set: the lane without a source, 0 resp. 63, reads 0)
 __device__ __forceinline__ double from_lower_lane(double v) {
     int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x138, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double from_upper_lane(double v) {
     int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x130, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
+}
+
+// A value every lane of the wave holds alike, moved to scalar registers (so
+// that what is derived from it, addresses above all, stays scalar too).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uniform(long long v) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double uniform(double v) {
+    return __longlong_as_double(uniform((long long)__double_as_longlong(v)));
 }
 
 // ---------------------------------------------------------------- boundaries
@@ -275,7 +288,7 @@ __device__ __forceinline__ bool team_reduce(Team &tm, double part, double *base,
         if (threadIdx.x == 0) lds[0] = v;
     }
     __syncthreads();
-    out = lds[0];
+    out = uniform(lds[0]);
     __syncthreads();
     return true;
 }

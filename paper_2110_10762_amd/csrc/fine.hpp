@@ -11,6 +11,8 @@
 //       and column per step), and writes back the inner R x (64*XP - 2D)
 //       block.  y-neighbours are other registers of the same lane, x-neighbours
 //       come from DPP lane shifts.
+//   2D sliding window: a wave owns 64*XP columns and a segment of rows that
+//       it marches down, holding two rows per time level (see fine2d_sw).
 //   3D: one step per pass; a wave owns an (x, y) strip of 64*XP by R+2 and
 //       marches along z with three planes in registers.
 // Out-of-domain halo values are loaded from the odd reflection of the state
@@ -73,6 +75,20 @@ __global__ __launch_bounds__(64) void k_fine1d(const double *__restrict__ src, d
 }
 
 // ------------------------------------------------------------------ 2D
+// left + right neighbour of each of a lane's XP consecutive points of one row
+// (lane edges by DPP); every 2D kernel uses this order so they round alike.
+template <int XP>
+__device__ __forceinline__ void x_neighbour_sums(const double (&cur)[XP], double (&lr)[XP]) {
+    if constexpr (XP == 1) {
+        lr[0] = from_lower_lane(cur[0]) + from_upper_lane(cur[0]);
+    } else {
+        lr[0] = from_lower_lane(cur[XP - 1]) + cur[1];
+#pragma unroll
+        for (int e = 1; e < XP - 1; ++e) lr[e] = cur[e - 1] + cur[e + 1];
+        lr[XP - 1] = cur[XP - 2] + from_upper_lane(cur[0]);
+    }
+}
+
 template <int XP, int R, int D>
 struct Shape2D {
     static constexpr int H = R + 2 * D;          // rows held per lane
@@ -110,14 +126,7 @@ __device__ __forceinline__ void fine2d_strip(const double *__restrict__ src, dou
             double cur[XP], lr[XP];
 #pragma unroll
             for (int e = 0; e < XP; ++e) cur[e] = c[e][j];
-            if constexpr (XP == 1) {
-                lr[0] = from_lower_lane(cur[0]) + from_upper_lane(cur[0]);
-            } else {
-                lr[0] = from_lower_lane(cur[XP - 1]) + cur[1];
-#pragma unroll
-                for (int e = 1; e < XP - 1; ++e) lr[e] = cur[e - 1] + cur[e + 1];
-                lr[XP - 1] = cur[XP - 2] + from_upper_lane(cur[0]);
-            }
+            x_neighbour_sums<XP>(cur, lr);
 #pragma unroll
             for (int e = 0; e < XP; ++e) {
                 c[e][j] = euler_update(cur[e], lr[e], prev[e] + c[e][j + 1], 4.0, r);
@@ -162,6 +171,153 @@ __global__ __launch_bounds__(BLOCK) void k_fine2d(const double *__restrict__ src
     const int sy = rem % nsy;          // vertical neighbours are consecutive waves
     const int sx = rem / nsy;
     fine2d_strip<XP, R, D>(src + st * sstride, dst + st * dstride, n, r, steps, sx, sy);
+}
+
+// ---- 2D sliding window
+// A wave owns the same 64*XP columns as a register strip (useful width
+// W = 64*XP - 2D), but a segment [ya, yb) of output rows that it marches
+// through one input row at a time.  For every time level t < D it keeps the
+// two most recent rows of that level in registers, so level t+1 of the row
+// one behind is formed as soon as level t of the newest row exists, and level
+// D leaves for HBM D rows behind the input.  Levels t >= steps (the short last
+// pass of a slice) use coefficient 0, which copies the value exactly, so every
+// pass runs the same branch-free code.  Only the 2D halo rows of a segment and
+// the 2D halo columns of a strip are computed twice.  Odd segments march
+// upwards: two neighbouring segments then read their shared halo rows at the
+// same time (the second read hits L2).  Addition is commutative, so the
+// direction does not change a single bit; the update order is that of the
+// register strip.
+// Row counts of at least this select the sliding window in shape tables and
+// kernel templates (register strips hold at most 64 rows).
+constexpr int SW_MIN_ROWS = 96;
+
+// Odd reflection of row y (wave-uniform, so scalar work): the interior row
+// to read and its sign.
+__device__ __forceinline__ int reflect_row(int y, int n, double &ys) {
+    const int P = 2 * (n + 1);
+    int t = y + 1;
+    if (t < 0 || t >= P) {
+        t %= P;
+        if (t < 0) t += P;
+    }
+    int yi = t - 1;
+    ys = 1.0;
+    if (t == 0 || t == n + 1) {
+        yi = 0;
+        ys = 0.0;
+    } else if (t > n) {
+        yi = P - t - 1;
+        ys = -1.0;
+    }
+    return __builtin_amdgcn_readfirstlane(yi);
+}
+
+// Issues the loads of row yi (no wait: the values are used PF rows later).
+template <int XP>
+__device__ __forceinline__ void issue_row2d(const double *__restrict__ src, int n, int yi, const unsigned (&xo)[XP],
+                                            double (&v)[XP]) {
+    const char *row = reinterpret_cast<const char *>(src + (long long)yi * n);
+#pragma unroll
+    for (int e = 0; e < XP; ++e) v[e] = *reinterpret_cast<const double *>(row + xo[e]);
+}
+
+template <int XP, int D>
+struct ShapeSW {
+    static constexpr int W = WAVE * XP - 2 * D;
+    static constexpr int PF = XP >= 4 ? 4 : 8;   // input rows in flight ahead of the window
+};
+
+// PF: input rows in flight ahead of the window (more hides HBM latency, fewer
+// saves registers).
+template <int XP, int D, int PF = ShapeSW<XP, D>::PF>
+__device__ __forceinline__ void fine2d_sw(const double *__restrict__ src, double *__restrict__ dst, int n,
+                                          double r, int steps, int sx, int ya, int yb, bool upward) {
+    constexpr int W = ShapeSW<XP, D>::W;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int x0 = sx * W - D;
+    unsigned xo[XP];   // byte offsets of the lane's columns (reflected)
+    double xs[XP];
+    bool own[XP];
+#pragma unroll
+    for (int e = 0; e < XP; ++e) {
+        const int lx = lane * XP + e;
+        xo[e] = (unsigned)reflect(x0 + lx, n, xs[e]) * 8u;
+        own[e] = lx >= D && lx < D + W && x0 + lx < n;
+    }
+    double rt[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) rt[t] = t < steps ? r : 0.0;
+    double w0[D][XP], w1[D][XP];   // level t: the rows two and one behind its newest
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+#pragma unroll
+        for (int e = 0; e < XP; ++e) w0[t][e] = w1[t][e] = 0.0;
+    // input rows ya-D .. yb+D-1 in march order; raw values and row signs in a ring
+    const int dir = upward ? -1 : 1;
+    const int first = upward ? yb - 1 + D : ya - D;
+    const int nrows = (yb - ya) + 2 * D;
+    double pf[PF][XP], ps[PF];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int yi = reflect_row(first + dir * q, n, ps[q]);
+        if (q < nrows) {
+            issue_row2d<XP>(src, n, yi, xo, pf[q]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < XP; ++e) pf[q][e] = 0.0;
+        }
+    }
+    for (int kb = 0; kb < nrows; kb += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = kb + q;
+            double c[XP];
+#pragma unroll
+            for (int e = 0; e < XP; ++e) c[e] = (ps[q] * xs[e]) * pf[q][e];
+            if (k + PF < nrows) {
+                const int yi = reflect_row(first + dir * (k + PF), n, ps[q]);
+                issue_row2d<XP>(src, n, yi, xo, pf[q]);
+            }
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                double lr[XP];
+                x_neighbour_sums<XP>(w1[t], lr);
+#pragma unroll
+                for (int e = 0; e < XP; ++e) {
+                    const double nx = euler_update(w1[t][e], lr[e], w0[t][e] + c[e], 4.0, rt[t]);
+                    w0[t][e] = w1[t][e];
+                    w1[t][e] = c[e];
+                    c[e] = nx;
+                }
+            }
+            const int y = first + dir * (k - D);
+            if (k < nrows && y >= ya && y < yb) {
+                double *row = dst + (long long)y * n;
+#pragma unroll
+                for (int e = 0; e < XP; ++e)
+                    if (own[e]) row[x0 + lane * XP + e] = c[e];
+            }
+        }
+    }
+}
+
+// Output rows [sy*ry, sy*ry + ry) of strip sx; vertical neighbours are
+// consecutive waves.
+template <int XP, int D>
+__global__ __launch_bounds__(BLOCK) void k_fine2d_sw(const double *__restrict__ src, double *__restrict__ dst,
+                                                     long long sstride, long long dstride, int n, double r,
+                                                     int steps, int nsx, int nsy, int ry, int count, int nblk) {
+    const int L = xcd_remap(blockIdx.x, nblk);
+    if (L >= nblk) return;
+    const long long wv = (long long)L * WAVES_PER_BLOCK + wave_id();
+    const long long per_state = (long long)nsx * nsy;
+    if (wv >= per_state * count) return;
+    const int st = (int)(wv / per_state);
+    const int rem = (int)(wv - (long long)st * per_state);
+    const int sy = rem % nsy;
+    const int sx = rem / nsy;
+    const int ya = sy * ry;
+    fine2d_sw<XP, D>(src + st * sstride, dst + st * dstride, n, r, steps, sx, ya, min(n, ya + ry), sy & 1);
 }
 
 // ------------------------------------------------------------------ 3D

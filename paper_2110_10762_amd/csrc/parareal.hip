@@ -48,16 +48,32 @@ static int fail(int code, const char *fmt, ...) {
 extern "C" const char *pr_last_error(void) { return g_err.c_str(); }
 
 // ------------------------------------------------------------------ shapes
+// 2D: (x points per lane, rows, depth); rows >= SW_MIN_ROWS is a sliding
+// window over segments of that many rows, fewer is a register strip.
 struct Shape {
     int xp, r, d;
+    bool sliding() const { return r >= SW_MIN_ROWS; }
 };
-static const Shape kShapes2D[] = {{2, 32, 1}, {2, 32, 2}, {2, 32, 4}, {2, 32, 8}, {2, 16, 8},
-                                  {2, 24, 12}, {2, 16, 16}, {1, 64, 8}, {2, 16, 4}, {2, 8, 4}};
+static const Shape kShapes2D[] = {{2, 32, 1},  {2, 32, 2},   {2, 32, 4},  {2, 32, 8},  {2, 16, 8},
+                                  {2, 24, 12}, {2, 16, 16},  {1, 64, 8},  {2, 16, 4},  {2, 8, 4},
+                                  {2, 128, 4}, {3, 128, 4},  {2, 128, 8}, {3, 128, 8}, {4, 128, 8},
+                                  {3, 256, 8}, {2, 128, 16}, {3, 96, 8},  {2, 128, 1}, {3, 128, 12}};
 static const Shape kShapes3D[] = {{2, 8, 1}, {2, 16, 1}, {1, 16, 1}, {2, 4, 1}};
-static const int kDefault2D = 4;   // (2, 16, 8)
+static const int kDefault2D = 12;        // sliding window (2, 128, 8): batches of states
+static const int kDefault2DSingle = 4;   // register strip (2, 16, 8): one state (more waves)
 static const int kDefault3D = 0;   // (2, 8, 1)
 static const int kNum2D = sizeof(kShapes2D) / sizeof(kShapes2D[0]);
 static const int kNum3D = sizeof(kShapes3D) / sizeof(kShapes3D[0]);
+
+// first table entry matching every given (> 0) parameter, or -1
+static int find_shape(int dim, int d, int r, int xp) {
+    const Shape *tab = dim == 2 ? kShapes2D : kShapes3D;
+    const int cnt = dim == 2 ? kNum2D : (dim == 3 ? kNum3D : 0);
+    for (int i = 0; i < cnt; ++i)
+        if ((d <= 0 || (dim == 2 ? tab[i].d : 1) == d) && (r <= 0 || tab[i].r == r) && (xp <= 0 || tab[i].xp == xp))
+            return i;
+    return -1;
+}
 
 static int r1d_for(int n) {   // registers per lane for a 1D state
     int R = 1;
@@ -96,7 +112,7 @@ struct pr_problem {
     std::vector<Buf> allocs;
     // synchronous workspace (single problem)
     double *v = nullptr, *w = nullptr, *tmp = nullptr, *wn = nullptr, *d0 = nullptr, *d1 = nullptr;
-    double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *cg_q = nullptr, *red = nullptr;
+    double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *red = nullptr;
     double *inv_tab = nullptr;        // 1D Thomas factors, padded
     unsigned *ctr = nullptr;          // team barrier counters
     Control *ctl = nullptr;
@@ -155,7 +171,8 @@ static int derive(const pr_config &c, Prob &P) {
     if (c.dim < 1 || c.dim > 3) return fail(PR_EINVAL, "dim must be 1, 2 or 3 (got %d)", c.dim);
     if (c.n < 1) return fail(PR_EINVAL, "n must be >= 1 (got %d)", c.n);
     if (c.dim == 1 && c.n > kMax1D) return fail(PR_EINVAL, "1D supports n <= %d (got %d)", kMax1D, c.n);
-    if (c.dim == 3 && c.n > 2048) return fail(PR_EINVAL, "3D supports n <= 2048");
+    if (c.dim >= 2 && std::pow((double)c.n, c.dim) >= 2147483647.0)
+        return fail(PR_EINVAL, "a %dD state must hold fewer than 2^31 points (n = %d)", c.dim, c.n);
     if (!(c.nu > 0) || !std::isfinite(c.nu)) return fail(PR_EINVAL, "nu must be > 0");
     if (!(c.T > 0) || !std::isfinite(c.T)) return fail(PR_EINVAL, "T must be > 0");
     if (c.nslices < 1) return fail(PR_EINVAL, "nslices must be >= 1");
@@ -188,18 +205,14 @@ static int derive(const pr_config &c, Prob &P) {
     P.kmax = (c.kmax <= 0 || c.kmax > c.nslices) ? c.nslices : c.kmax;
     P.eps = c.eps;
     P.shape = P.dim == 2 ? kDefault2D : (P.dim == 3 ? kDefault3D : 0);
-    if (c.tb_depth > 0 || c.tile_rows > 0) {
-        const Shape *tab = P.dim == 2 ? kShapes2D : kShapes3D;
-        const int cnt = P.dim == 2 ? kNum2D : (P.dim == 3 ? kNum3D : 0);
-        int found = -1;
-        for (int i = 0; i < cnt; ++i)
-            if ((c.tb_depth <= 0 || tab[i].d == c.tb_depth) && (c.tile_rows <= 0 || tab[i].r == c.tile_rows)) {
-                found = i;
-                break;
-            }
-        if (P.dim != 1 && found < 0)
-            return fail(PR_EINVAL, "no fine-kernel shape with depth %d and %d rows", c.tb_depth, c.tile_rows);
-        if (found >= 0) P.shape = found;
+    P.shape1 = P.dim == 2 ? kDefault2DSingle : -1;
+    if (P.dim > 1 && (c.tb_depth > 0 || c.tile_rows > 0 || c.fine_xpts > 0)) {
+        P.shape1 = -1;
+        const int found = find_shape(P.dim, c.tb_depth, c.tile_rows, c.fine_xpts);
+        if (found < 0)
+            return fail(PR_EINVAL, "no fine-kernel shape with depth %d, %d rows and %d x points per lane",
+                        c.tb_depth, c.tile_rows, c.fine_xpts);
+        P.shape = found;
     }
     return PR_OK;
 }
@@ -217,8 +230,34 @@ static void launch2d(hipStream_t st, const double *src, double *dst, long long s
                        nsx, nsy, count, nblk);
 }
 
+template <int XP, int D>
+static void launch2d_sw(hipStream_t st, const double *src, double *dst, long long ss, long long ds, int n,
+                        double r, int steps, int count, int ry) {
+    constexpr int W = ShapeSW<XP, D>::W;
+    const int nsx = (n + W - 1) / W, nsy = (n + ry - 1) / ry;
+    const long long waves = (long long)nsx * nsy * count;
+    const int nblk = (int)((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
+    const int grid = 8 * ((nblk + 7) / 8);
+    hipLaunchKernelGGL((k_fine2d_sw<XP, D>), dim3(grid), dim3(BLOCK), 0, st, src, dst, ss, ds, n, r, steps, nsx,
+                       nsy, ry, count, nblk);
+}
+
 static void launch2d_shape(int shape, hipStream_t st, const double *src, double *dst, long long ss,
                            long long ds, int n, double r, int steps, int count) {
+    const int ry = kShapes2D[shape].r;
+    switch (shape) {
+        case 10: launch2d_sw<2, 4>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 11: launch2d_sw<3, 4>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 12: launch2d_sw<2, 8>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 13: launch2d_sw<3, 8>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 14: launch2d_sw<4, 8>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 15: launch2d_sw<3, 8>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 16: launch2d_sw<2, 16>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 17: launch2d_sw<3, 8>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 18: launch2d_sw<2, 1>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 19: launch2d_sw<3, 12>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        default: break;
+    }
     switch (shape) {
         case 0: launch2d<2, 32, 1>(st, src, dst, ss, ds, n, r, steps, count); break;
         case 1: launch2d<2, 32, 2>(st, src, dst, ss, ds, n, r, steps, count); break;
@@ -290,7 +329,13 @@ static int run_fine(pr_problem *h, const Prob &P, const double *src, double *dst
         HIPCHK(hipGetLastError());
         return PR_OK;
     }
-    const int D = fine_depth(P);
+    int shape = P.shape;
+    if (count == 1 && P.dim == 2 && P.shape1 >= 0) {
+        // a single state: the shape made for one state, unless it needs a scratch buffer there is none of
+        const int d1 = kShapes2D[P.shape1].d;
+        if ((steps + d1 - 1) / d1 <= 1 || tmp) shape = P.shape1;
+    }
+    const int D = P.dim == 2 ? kShapes2D[shape].d : 1;
     const int passes = (steps + D - 1) / D;
     if (passes > 1 && !tmp) return fail(PR_EINVAL, "internal: fine pass needs a scratch buffer");
     const double *cur = src;
@@ -300,9 +345,9 @@ static int run_fine(pr_problem *h, const Prob &P, const double *src, double *dst
         double *tgt = ((passes - 1 - p) % 2 == 0) ? dst : tmp;
         const long long ts = (tgt == dst) ? ds : P.npts;
         if (P.dim == 2)
-            launch2d_shape(P.shape, h->stream, cur, tgt, cs, ts, P.n, P.r, st, count);
+            launch2d_shape(shape, h->stream, cur, tgt, cs, ts, P.n, P.r, st, count);
         else
-            launch3d_shape(P.shape, h->stream, cur, tgt, cs, ts, P.n, P.r, count);
+            launch3d_shape(shape, h->stream, cur, tgt, cs, ts, P.n, P.r, count);
         HIPCHK(hipGetLastError());
         cur = tgt;
         cs = ts;
@@ -359,7 +404,7 @@ static SweepArgs sweep_args(pr_problem *h, const Prob &P, double *lam) {
     a.g = P.g;
     a.cg_tol = P.cg_tol;
     a.cg_maxit = P.cg_maxit;
-    a.wk = CGWork{h->cg_r, h->cg_p0, h->cg_p1, h->cg_q, h->red};
+    a.wk = CGWork{h->cg_r, h->cg_p0, h->cg_p1, h->red};
     a.ctr = h->ctr;
     a.ctl = h->ctl;
     return a;
@@ -404,7 +449,6 @@ static int alloc_sync(pr_problem *h) {
         if ((rc = alloc_t(h, &h->cg_r, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_p0, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_p1, P.npts))) return rc;
-        if ((rc = alloc_t(h, &h->cg_q, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->d0, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->d1, P.npts))) return rc;
     }
@@ -505,56 +549,63 @@ extern "C" int pr_get_info(const pr_problem *h, int problem, pr_info *out) {
     out->s = P.s;
     out->npts = P.npts;
     out->offset = P.off_lam;
+    out->sliding = 0;
     if (P.dim == 2) {
         out->tb_depth = kShapes2D[P.shape].d;
         out->tile_rows = kShapes2D[P.shape].r;
+        out->xpts = kShapes2D[P.shape].xp;
+        out->sliding = kShapes2D[P.shape].sliding() ? 1 : 0;
     } else if (P.dim == 3) {
         out->tb_depth = 1;
         out->tile_rows = kShapes3D[P.shape].r;
+        out->xpts = kShapes3D[P.shape].xp;
     } else {
         out->tb_depth = P.m;
         out->tile_rows = 1;
+        out->xpts = r1d_for(P.n);
     }
     return PR_OK;
 }
 
 extern "C" int pr_fine_shape_count(int dim) { return dim == 2 ? kNum2D : (dim == 3 ? kNum3D : (dim == 1 ? 1 : 0)); }
 
-extern "C" int pr_fine_shape_get(int dim, int index, int *tb_depth, int *tile_rows, int *xpts) {
+extern "C" int pr_fine_shape_get(int dim, int index, int *tb_depth, int *tile_rows, int *xpts, int *sliding) {
     if (dim == 2 && index >= 0 && index < kNum2D) {
         if (tb_depth) *tb_depth = kShapes2D[index].d;
         if (tile_rows) *tile_rows = kShapes2D[index].r;
         if (xpts) *xpts = kShapes2D[index].xp;
+        if (sliding) *sliding = kShapes2D[index].sliding() ? 1 : 0;
         return PR_OK;
     }
     if (dim == 3 && index >= 0 && index < kNum3D) {
         if (tb_depth) *tb_depth = 1;
         if (tile_rows) *tile_rows = kShapes3D[index].r;
         if (xpts) *xpts = kShapes3D[index].xp;
+        if (sliding) *sliding = 0;
         return PR_OK;
     }
     return fail(PR_EINVAL, "no shape %d for dim %d", index, dim);
 }
 
-extern "C" int pr_set_fine_shape(pr_problem *h, int problem, int tb_depth, int tile_rows) {
+extern "C" int pr_set_fine_shape(pr_problem *h, int problem, int tb_depth, int tile_rows, int xpts) {
     if (!h) return fail(PR_EINVAL, "NULL handle");
     if (problem < 0 || problem >= (int)h->P.size()) return fail(PR_EINVAL, "problem index out of range");
     Prob &P = h->P[problem];
     if (P.dim == 1) return PR_OK;
-    const Shape *tab = P.dim == 2 ? kShapes2D : kShapes3D;
-    const int cnt = P.dim == 2 ? kNum2D : kNum3D;
-    for (int i = 0; i < cnt; ++i)
-        if (tab[i].d == tb_depth && tab[i].r == tile_rows) {
-            const int old_passes = (P.m + fine_depth(P) - 1) / fine_depth(P);
-            P.shape = i;
-            const int passes = (P.m + fine_depth(P) - 1) / fine_depth(P);
-            if (h->P.size() == 1 && passes > 1 && old_passes <= 1 && !h->tmp) {
-                int rc = alloc_t(h, &h->tmp, (size_t)(P.N + 1) * P.npts);
-                if (rc) return rc;
-            }
-            return PR_OK;
-        }
-    return fail(PR_EINVAL, "no fine-kernel shape with depth %d and %d rows", tb_depth, tile_rows);
+    const int i = find_shape(P.dim, tb_depth, tile_rows, xpts);
+    if (i < 0)
+        return fail(PR_EINVAL, "no fine-kernel shape with depth %d, %d rows and %d x points per lane", tb_depth,
+                    tile_rows, xpts);
+    const int old_passes = (P.m + fine_depth(P) - 1) / fine_depth(P);
+    P.shape = i;
+    P.shape1 = -1;
+    const int passes = (P.m + fine_depth(P) - 1) / fine_depth(P);
+    if (h->P.size() == 1 && passes > 1 && old_passes <= 1 && !h->tmp) {
+        int rc = alloc_t(h, &h->tmp, (size_t)(P.N + 1) * P.npts);
+        if (rc) return rc;
+    }
+    if (h->bw_ready) h->bw_dirty = true;
+    return PR_OK;
 }
 
 // ------------------------------------------------------------------ helpers for solves
@@ -633,7 +684,7 @@ extern "C" int pr_apply_coarse(pr_problem *h, const double *in, double *out, int
     Geom g = P.g;
     double s = P.s, tol = P.cg_tol;
     int maxit = P.cg_maxit;
-    CGWork wk{h->cg_r, h->cg_p0, h->cg_p1, h->cg_q, h->red};
+    CGWork wk{h->cg_r, h->cg_p0, h->cg_p1, h->red};
     unsigned *ctr = h->ctr;
     Control *ctl = h->ctl;
     unsigned long long *ci = h->iscal;

@@ -52,7 +52,7 @@ def test_fine_1d(n, steps):
         assert rel(got[c], heat.fine(x[c], r, steps)) <= 1e-12
 
 
-@pytest.mark.parametrize("n", [63, 100, 1])
+@pytest.mark.parametrize("n", [63, 100, 1, 300])
 def test_fine_2d_all_shapes_bitwise_and_vs_oracle(n):
     rng = np.random.default_rng(7 + n)
     cnt = 3
@@ -62,8 +62,8 @@ def test_fine_2d_all_shapes_bitwise_and_vs_oracle(n):
     steps = 19
     want = [heat.fine(x[c], r, steps) for c in range(cnt)]
     ref_bits = None
-    for (d, rows, xp) in pr.fine_shapes(2):
-        prob.set_fine_shape(d, rows)
+    for (d, rows, xp, sw) in pr.fine_shapes(2):
+        prob.set_fine_shape(d, rows, xp)
         y = torch.empty_like(dev(x))
         prob.apply_fine(dev(x), y, cnt, steps)
         got = y.cpu().numpy()
@@ -84,8 +84,8 @@ def test_fine_3d_all_shapes(n):
     steps = 5
     want = [heat.fine(x[c], r, steps) for c in range(2)]
     ref_bits = None
-    for (d, rows, xp) in pr.fine_shapes(3):
-        prob.set_fine_shape(d, rows)
+    for (d, rows, xp, sw) in pr.fine_shapes(3):
+        prob.set_fine_shape(d, rows, xp)
         y = torch.empty_like(dev(x))
         prob.apply_fine(dev(x), y, 2, steps)
         got = y.cpu().numpy()
