@@ -116,6 +116,10 @@ typedef struct pr_stats {
     int    teams;            /* async: concurrent slice teams used */
     long long copy_retries;  /* async: predecessor copies redone (slot overwritten meanwhile) */
     long long idle_rounds;   /* async: team rounds with nothing to update */
+    /* async: mean per team of the time its leader saw in each phase of its
+       updates (fine propagation, predecessor copy, coarse solve, correction
+       and publication) and of the whole launch; the rest is idle waiting */
+    double team_fine_ms, team_copy_ms, team_coarse_ms, team_corr_ms, team_total_ms;
 } pr_stats;
 
 /* Asynchronous-driver options (Algorithm 2 emulated by persistent teams). */
@@ -125,7 +129,9 @@ typedef struct pr_stats {
 
 typedef struct pr_async_opts {
     int mode;                /* PR_ASYNC_* */
-    int teams;               /* concurrent slice teams; 0 = automatic */
+    int teams;               /* concurrent slice teams, each taking its slices round-robin;
+                                0 = automatic: one per slice in 1D and in REPLAY (which
+                                needs it), else one per XCD (8 on MI355X) */
     int max_local_iters;     /* cap on k_i (<= 0: 4*N + 16) */
     const int *schedule;     /* REPLAY: host array [N][max_local_iters]: predecessor
                                 version read by slice i's k-th coarse solve (slice 1: 0) */

@@ -67,6 +67,9 @@ class pr_stats(ctypes.Structure):
         ("kernel_updates", ctypes.c_longlong),
         ("teams", ctypes.c_int), ("copy_retries", ctypes.c_longlong),
         ("idle_rounds", ctypes.c_longlong),
+        ("team_fine_ms", ctypes.c_double), ("team_copy_ms", ctypes.c_double),
+        ("team_coarse_ms", ctypes.c_double), ("team_corr_ms", ctypes.c_double),
+        ("team_total_ms", ctypes.c_double),
     ]
 
 

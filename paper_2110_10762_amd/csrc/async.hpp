@@ -80,7 +80,7 @@ struct AsyncWork {
     unsigned long long *counters = nullptr;
     void *args = nullptr;   // the launch's AsyncArgs, in device memory
     // the configuration these buffers were sized for
-    int R = 0, L = 0, nteams = 0, grid = 0, maxtsz = 0, withS = 0;
+    int R = 0, L = 0, nteams = 0, grid = 0, withS = 0;   // nteams: CG sets held
 };
 
 struct AsyncArgs {
@@ -104,7 +104,8 @@ struct AsyncArgs {
     unsigned *tctr;          // [nteams * 16]
     long long *tbc;          // [nteams * 16] leader broadcasts
     double *tred;            // [nteams * 2 * maxtsz]
-    double *cgr, *cgp0, *cgp1;   // [nteams * npts]
+    double *cgr, *cgp0, *cgp1;   // [nteams * cgs]
+    long long cgs;               // per-team stride of the CG vectors
     Control *ctl;
     unsigned long long *counters;   // cg iterations, coarse solves, skipped solves, copy retries, idle rounds
     // fine-kernel geometry
@@ -299,8 +300,8 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
     Team tm{a.tctr + (long long)team * team_counter_words(a.maxtsz), a.ctl, a.tsize[team], rank, 0u};
     if (!team_setup(tm)) return;
     long long *bc = a.tbc + team * 16;
-    CGWork wk{a.cgr + (long long)team * a.npts, a.cgp0 + (long long)team * a.npts,
-              a.cgp1 + (long long)team * a.npts,
+    CGWork wk{a.cgr + (long long)team * a.cgs, a.cgp0 + (long long)team * a.cgs,
+              a.cgp1 + (long long)team * a.cgs,
               a.tred + (long long)team * 2 * a.maxtsz};
     __shared__ double lds[MAX_WAVES];
     const bool leader = (rank == 0 && threadIdx.x == 0);
@@ -308,6 +309,8 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
     const long long all = (long long)(a.N + 1) * np;
     const unsigned long long t0 = wall_clock64();
     unsigned long long cg_its = 0, g_solves = 0, g_skips = 0, retries = 0, idles = 0;
+    // wall-clock ticks the team spends per phase (leader's view)
+    unsigned long long t_fine = 0, t_copy = 0, t_coarse = 0, t_corr = 0, tp = 0;
 
     for (;;) {
         bool any_active = false, any_work = false;
@@ -389,7 +392,13 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
             double *w_new = a.W + (wo ^ 1) * all + i * np;
             double *v = a.V + i * np;
             // ---------------- v = F(x_old)
+            if (leader) tp = wall_clock64();
             if (!team_fine<DIM, XP, RR, D>(tm, a, x_old, v, a.S ? a.S + i * np : nullptr)) goto out;
+            if (leader) {
+                const unsigned long long t = wall_clock64();
+                t_fine += t - tp;
+                tp = t;
+            }
             // ---------------- newest predecessor (FREE/EXACT read it after F)
             double drift_read = 0.0;
             int g_final = 0;
@@ -449,6 +458,11 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
                 }
             }
             // ---------------- w_new = G(x_new) (or G(x_new - x_old)), or nothing if stale
+            if (leader) {
+                const unsigned long long t = wall_clock64();
+                t_copy += t - tp;
+                tp = t;
+            }
             const double *wv = w_old;
             if (!stale) {
                 int it;
@@ -467,6 +481,11 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
                 ++g_skips;
             }
             // ---------------- lambda = v + (w_new - w_old), change norm, write the next slot
+            if (leader) {
+                const unsigned long long t = wall_clock64();
+                t_coarse += t - tp;
+                tp = t;
+            }
             const int nslot = (myver + 1) % a.R;
             const double *cur = a.ring + (long long)(myver % a.R) * all + i * np;
             double *nxt = a.ring + (long long)nslot * all + i * np;
@@ -507,6 +526,7 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
                     __hip_atomic_store(&a.ctl->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 if (a.mode == AMODE_FREE && delta < a.eps && free_stop_rule(a))
                     __hip_atomic_store(&a.ctl->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                t_corr += wall_clock64() - tp;
             }
         }
         if (!any_active) {
@@ -532,6 +552,11 @@ out:
         __hip_atomic_fetch_add(&a.counters[2], g_skips, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&a.counters[3], retries, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&a.counters[4], idles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.counters[5], t_fine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.counters[6], t_copy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.counters[7], t_coarse, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.counters[8], t_corr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.counters[9], wall_clock64() - t0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -82,6 +82,7 @@ static int r1d_for(int n) {   // registers per lane for a 1D state
 }
 static const int kMax1D = 32 * WAVE;   // 2048 points
 static const int SWEEP_BLOCK = 1024;   // threads per workgroup of the whole-GPU coarse sweeps
+static const int kXcds = 8;            // MI355X: accelerator complex dies (each with its own L2)
 
 // ------------------------------------------------------------------ handle
 struct Prob {
@@ -633,6 +634,7 @@ static void stats_reset(pr_stats *st) {
     st->kernel_ms = 0;
     st->kernel_cg_iters = st->kernel_updates = 0;
     st->copy_retries = st->idle_rounds = 0;
+    st->team_fine_ms = st->team_copy_ms = st->team_coarse_ms = st->team_corr_ms = st->team_total_ms = 0;
 }
 
 // ------------------------------------------------------------------ apply entry points

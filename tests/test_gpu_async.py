@@ -124,7 +124,7 @@ def test_exact_mode_finite_termination_bitwise(which):
     assert np.array_equal(lam, ser.cpu().numpy())
 
 
-@pytest.mark.parametrize("which,teams", [("1d", 0), ("1d", 3), ("2d", 0), ("2d", 2), ("3d", 0)])
+@pytest.mark.parametrize("which,teams", [("1d", 0), ("1d", 3), ("2d", 0), ("2d", 2), ("2d", 3), ("2d", 8), ("3d", 0), ("3d", 4)])
 def test_free_mode_reaches_fixed_point(which, teams):
     if which == "1d":
         p = workloads.heat1d()
