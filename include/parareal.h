@@ -126,6 +126,12 @@ typedef struct pr_stats {
 #define PR_ASYNC_FREE    0   /* read the newest predecessor; tolerance stop */
 #define PR_ASYNC_EXACT   1   /* run until the finite-termination cascade reaches slice N */
 #define PR_ASYNC_REPLAY  2   /* read the versions a host schedule names (deterministic) */
+#define PR_ASYNC_PIPELINED 3 /* Algorithm 1: the synchronous iteration with per-slice waits
+                                instead of a barrier (update k of slice i waits for version
+                                k+1 of slice i-1); stops at the first k whose change is below
+                                eps, detected on the device; output = that iterate, the same
+                                as pr_solve_sync's.  Keeps every version ((N+2)(N+1)
+                                states). */
 
 typedef struct pr_async_opts {
     int mode;                /* PR_ASYNC_* */
@@ -139,6 +145,11 @@ typedef struct pr_async_opts {
                                 (emulates slow processors / late messages); NULL = none */
     double time_limit_s;     /* device-side wall-clock cap of one solve (<= 0: 120 s); the
                                 launch stops and the call returns PR_ETIMEOUT past it */
+    double latency_us;       /* emulated message latency: a published version becomes
+                                readable by the successor this long after publication
+                                (0 = none; at most 1e7) */
+    int slice_blocks;        /* which slices a team holds: 1 = a contiguous block, 2 = every
+                                teams-th slice; 0 = default (blocks) */
 } pr_async_opts;
 
 /* Create a handle for one problem (nproblems == 1) or a batch of independent

@@ -30,6 +30,7 @@ PR_COARSE_CG = 2
 PR_ASYNC_FREE = 0
 PR_ASYNC_EXACT = 1
 PR_ASYNC_REPLAY = 2
+PR_ASYNC_PIPELINED = 3
 
 
 class pr_config(ctypes.Structure):
@@ -77,7 +78,8 @@ class pr_async_opts(ctypes.Structure):
     _fields_ = [
         ("mode", ctypes.c_int), ("teams", ctypes.c_int), ("max_local_iters", ctypes.c_int),
         ("schedule", ctypes.POINTER(ctypes.c_int)), ("delay_spins", ctypes.POINTER(ctypes.c_int)),
-        ("time_limit_s", ctypes.c_double),
+        ("time_limit_s", ctypes.c_double), ("latency_us", ctypes.c_double),
+        ("slice_blocks", ctypes.c_int),
     ]
 
 
@@ -251,10 +253,12 @@ class Problem:
     def set_async_options(self, mode=PR_ASYNC_FREE, teams=0, max_local_iters=0,
                           schedule: Optional[Sequence[int]] = None,
                           delay_spins: Optional[Sequence[int]] = None,
-                          time_limit_s: float = 0.0):
+                          time_limit_s: float = 0.0, latency_us: float = 0.0, slice_blocks: int = 0):
         o = pr_async_opts()
         o.mode, o.teams, o.max_local_iters = mode, teams, max_local_iters
         o.time_limit_s = time_limit_s
+        o.latency_us = latency_us
+        o.slice_blocks = slice_blocks
         keep = []
         if schedule is not None:
             arr = (ctypes.c_int * len(schedule))(*schedule)

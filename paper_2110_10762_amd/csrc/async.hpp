@@ -41,7 +41,9 @@
 
 namespace pr {
 
-constexpr int AMODE_FREE = 0, AMODE_EXACT = 1, AMODE_REPLAY = 2;
+constexpr int AMODE_FREE = 0, AMODE_EXACT = 1, AMODE_REPLAY = 2, AMODE_PIPELINED = 3;
+// modes that keep every version and read scheduled ones
+__host__ __device__ inline bool scheduled_reads(int mode) { return mode == AMODE_REPLAY || mode == AMODE_PIPELINED; }
 
 struct alignas(64) SliceHdr {
     int seq;          // sequence lock (odd while the fields change)
@@ -78,6 +80,9 @@ struct AsyncWork {
     double *tred = nullptr;
     double *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr;
     unsigned long long *counters = nullptr;
+    unsigned long long *pub_t = nullptr;   // [(N+1) R] publication time of each slot's version
+    int *pipe = nullptr;                   // PIPELINED: [N+2] publications per version, then K*
+    unsigned long long *pipe_dmax = nullptr;   // PIPELINED: [N+2] max change per version (bits)
     void *args = nullptr;   // the launch's AsyncArgs, in device memory
     // the configuration these buffers were sized for
     int R = 0, L = 0, nteams = 0, grid = 0, withS = 0;   // nteams: CG sets held
@@ -99,6 +104,12 @@ struct AsyncArgs {
     double *slot_drift;      // [(N+1) R]
     const int *sched;        // REPLAY: [N][L]
     const int *delay;        // [N+1] or NULL
+    unsigned long long *pub_t;    // [(N+1) R] wall-clock time each slot's version was published
+    unsigned long long lat;       // ticks after publication before a version may be read
+    int *pipe;                    // PIPELINED: [N+1] publication counts per version, [N+1] = K*
+    unsigned long long *pipe_dmax;  // PIPELINED: [N+1] max change of each version (bits)
+    int kcap;                     // PIPELINED: iteration cap (k = N is exact)
+    int blocks;                   // slices per team: contiguous blocks (1) or every nteams-th (0)
     int nteams, maxtsz;
     const int *team_of, *rank_of, *tsize;   // per workgroup / per team
     unsigned *tctr;          // [nteams * 16]
@@ -171,6 +182,13 @@ __device__ __forceinline__ bool hdr_read(const SliceHdr *h, HdrView &o) {
     return s1 == s2;
 }
 
+__device__ __forceinline__ unsigned long long ld_relaxed_u64(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed_u64(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Double-collect snapshot of all headers; true if the FREE stop rule holds.
 __device__ bool free_stop_rule(const AsyncArgs &a) {
     long long vsum[2] = {0, 0};
@@ -190,6 +208,25 @@ __device__ bool free_stop_rule(const AsyncArgs &a) {
         if (!ok) return false;
     }
     return vsum[0] == vsum[1];
+}
+
+// Newest version of slice j a reader may use: with a message latency, a
+// version becomes readable `lat` ticks after its publication (the emulated
+// transfer); the reader then takes the newest one that has arrived, going
+// back at most to the oldest version the slot ring still protects (waiting
+// for that one if it is still in flight).
+__device__ int visible_version(const AsyncArgs &a, int j) {
+    const int newest = ld_acquire(&a.hdr[j].ver);
+    if (a.lat == 0) return newest;
+    const int oldest = max(0, newest - (a.R - 2));
+    for (int v = newest; v > oldest; --v)
+        if (wall_clock64() >= ld_relaxed_u64(&a.pub_t[j * a.R + v % a.R]) + a.lat) return v;
+    const unsigned long long due = ld_relaxed_u64(&a.pub_t[j * a.R + oldest % a.R]) + a.lat;
+    while (wall_clock64() < due) {
+        if (__hip_atomic_load(&a.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return oldest;
 }
 
 // ---- team-parallel elementwise helpers (chunks of 64 x-values)
@@ -292,7 +329,7 @@ enum { ACT_IDLE = 0, ACT_UPDATE = 1, ACT_DONE = 2 };
 // stay in scalar registers, where a by-value struct passed on by reference
 // would be copied to scratch.
 template <int DIM, int XP, int RR, int D>
-__global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ ap) {
+__global__ __launch_bounds__(BLOCK, DIM == 2 ? 3 : (DIM == 3 ? 2 : 1)) void k_async(const AsyncArgs *__restrict__ ap) {
     const AsyncArgs &a = *ap;
     const int team = a.team_of[blockIdx.x];
     if (team < 0) return;
@@ -314,7 +351,12 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
 
     for (;;) {
         bool any_active = false, any_work = false;
-        for (int i = team + 1; i <= a.N; i += a.nteams) {
+        // the team's slices: every nteams-th, or a contiguous block; visited in
+        // increasing order, one update each per round
+        const int i_first = a.blocks ? 1 + (int)((long long)team * a.N / a.nteams) : team + 1;
+        const int i_last = a.blocks ? (int)((long long)(team + 1) * a.N / a.nteams) : a.N;
+        const int i_step = a.blocks ? 1 : a.nteams;
+        for (int i = i_first; i <= i_last; i += i_step) {
             // ---------------- leader decides, team follows
             long long b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             if (leader) {
@@ -324,15 +366,37 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
                 // a final slice (EXACT) or one at its iteration cap publishes no more
                 if (L.done || a.hdr[i].k >= a.L || (a.mode == AMODE_EXACT && a.hdr[i].final_from >= 0)) {
                     action = ACT_DONE;
-                } else if (a.mode == AMODE_REPLAY) {
-                    const int tgt = a.sched[(long long)(i - 1) * a.L + a.hdr[i].k];
+                } else if (scheduled_reads(a.mode)) {
+                    // REPLAY: the host schedule.  PIPELINED (Algorithm 1): update k
+                    // reads version k+1 of the predecessor, or its last one, i-1,
+                    // once it is exact; slice i is exact after i updates, and
+                    // nothing past the stopping iteration K* is needed.  A team
+                    // holding several slices visits them in increasing order, one
+                    // update each per round, so the update it waits on only needs
+                    // updates of lower slices from this round or earlier ones:
+                    // every wait ends.
+                    const int k = a.hdr[i].k;
+                    int tgt;
+                    if (a.mode == AMODE_REPLAY) {
+                        tgt = a.sched[(long long)(i - 1) * a.L + k];
+                    } else {
+                        const int ks = ld_acquire(&a.pipe[a.N + 1]);
+                        tgt = (k >= i || k >= ks) ? -1 : min(k + 1, i - 1);
+                    }
                     if (tgt < 0) {
                         action = ACT_DONE;
                     } else {
                         pv = tgt;
                         if (i > 1) {
                             long long spins = 0;
-                            while (ld_acquire(&a.hdr[i - 1].ver) < tgt) {
+                            for (;;) {
+                                const int have = ld_acquire(&a.hdr[i - 1].ver);
+                                if (have >= tgt && wall_clock64() >= ld_relaxed_u64(&a.pub_t[(i - 1) * a.R + tgt % a.R]) + a.lat)
+                                    break;
+                                if (a.mode == AMODE_PIPELINED && k >= ld_acquire(&a.pipe[a.N + 1])) {
+                                    action = ACT_DONE;   // K* became known: this update is not needed
+                                    break;
+                                }
                                 if (__hip_atomic_load(&a.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
                                 if (++spins > SPIN_LIMIT) {
                                     __hip_atomic_store(&a.ctl->error, -7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -344,7 +408,7 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
                         }
                     }
                 } else {
-                    pv = (i == 1) ? 0 : ld_acquire(&a.hdr[i - 1].ver);
+                    pv = (i == 1) ? 0 : visible_version(a, i - 1);
                     const bool stale = (pv == L.f_ver);
                     if (a.idle_skip && stale && L.stale_streak >= 1) {
                         // Its last update already read this predecessor version, so
@@ -392,9 +456,9 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
             double *w_new = a.W + (wo ^ 1) * all + i * np;
             double *v = a.V + i * np;
             // ---------------- v = F(x_old)
-            if (leader) tp = wall_clock64();
+            tp = wall_clock64();
             if (!team_fine<DIM, XP, RR, D>(tm, a, x_old, v, a.S ? a.S + i * np : nullptr)) goto out;
-            if (leader) {
+            {   // uniform code: the phase clocks stay in scalar registers
                 const unsigned long long t = wall_clock64();
                 t_fine += t - tp;
                 tp = t;
@@ -406,10 +470,10 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
             double *dbuf = a.W + i * np;          // increment mode: change of the input
             double *ybuf = a.W + all + i * np;    // increment mode: G(change)
             for (;;) {
-                if (a.mode != AMODE_REPLAY) {
+                if (!scheduled_reads(a.mode)) {
                     long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                     if (leader) {
-                        c[0] = (i == 1) ? 0 : ld_acquire(&a.hdr[i - 1].ver);
+                        c[0] = (i == 1) ? 0 : visible_version(a, i - 1);
                         c[1] = (c[0] == a.loc[i].f_ver) ? 1 : 0;
                     }
                     if (!team_bcast(tm, bc, c)) goto out;
@@ -439,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
                     const int ff = __hip_atomic_load(&a.hdr[i - 1].final_from, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     const int after = (i == 1) ? pv : ld_acquire(&a.hdr[i - 1].ver);
-                    c[0] = (a.mode == AMODE_REPLAY || after - pv <= a.R - 2) ? 1 : 0;
+                    c[0] = (scheduled_reads(a.mode) || after - pv <= a.R - 2) ? 1 : 0;
                     c[1] = __double_as_longlong(dr);
                     c[2] = (i == 1) ? 1 : ((ff >= 0 && pv >= ff) ? 1 : 0);
                 }
@@ -458,7 +522,7 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
                 }
             }
             // ---------------- w_new = G(x_new) (or G(x_new - x_old)), or nothing if stale
-            if (leader) {
+            {   // uniform code: the phase clocks stay in scalar registers
                 const unsigned long long t = wall_clock64();
                 t_copy += t - tp;
                 tp = t;
@@ -481,7 +545,7 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
                 ++g_skips;
             }
             // ---------------- lambda = v + (w_new - w_old), change norm, write the next slot
-            if (leader) {
+            {   // uniform code: the phase clocks stay in scalar registers
                 const unsigned long long t = wall_clock64();
                 t_coarse += t - tp;
                 tp = t;
@@ -514,7 +578,25 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
                 const int gf = stale ? L.f_final : g_final;
                 int ff = h->final_from;
                 if (ff < 0 && L.f_final && gf) ff = myver + 1;
+                st_relaxed_u64(&a.pub_t[i * a.R + nslot], wall_clock64());   // ordered by the publication
                 hdr_publish(h, myver + 1, h->k + 1, pv, ff, delta, drift, sref);
+                if (a.mode == AMODE_PIPELINED) {
+                    // version v is complete once slices v..N have published it; the
+                    // first complete version with a change below eps (or v = N, or
+                    // the cap) is the stopping iteration K* of the synchronous test
+                    const int v = myver + 1;
+                    __hip_atomic_fetch_max(&a.pipe_dmax[v], (unsigned long long)__double_as_longlong(delta),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int seen = __hip_atomic_fetch_add(&a.pipe[v], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+                    if (seen == a.N - v + 1) {
+                        const double dv = __longlong_as_double((long long)__hip_atomic_load(
+                            &a.pipe_dmax[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        if (dv < a.eps || v >= a.kcap) {
+                            __hip_atomic_fetch_min(&a.pipe[a.N + 1], v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(&a.ctl->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
                 if (!stale) {
                     L.xo ^= 1;
                     if (!a.incr) L.wo ^= 1;
@@ -526,8 +608,8 @@ __global__ __launch_bounds__(BLOCK) void k_async(const AsyncArgs *__restrict__ a
                     __hip_atomic_store(&a.ctl->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 if (a.mode == AMODE_FREE && delta < a.eps && free_stop_rule(a))
                     __hip_atomic_store(&a.ctl->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                t_corr += wall_clock64() - tp;
             }
+            t_corr += wall_clock64() - tp;
         }
         if (!any_active) {
             // every slice of this team has retired: the state may now satisfy
@@ -560,6 +642,12 @@ out:
     }
 }
 
+// Pipelined driver: no version complete yet, stopping iteration unknown (N+1).
+__global__ void k_pipe_init(int *pipe, int N) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v <= N + 1) pipe[v] = (v == N + 1) ? N + 1 : 0;
+}
+
 // Initial per-slice control state: x_old = lambda_{i-1}^0 in X[0], w_old =
 // lambda_i^0 in W[0], version 0 in ring slot 0.
 __global__ void k_async_init(SliceHdr *hdr, SliceLoc *loc, double *slot_drift, int N, int R) {
@@ -575,12 +663,13 @@ __global__ void k_async_init(SliceHdr *hdr, SliceLoc *loc, double *slot_drift, i
     for (int j = 0; j < R; ++j) slot_drift[i * R + j] = 0.0;
 }
 
-// lambda_out[i] = newest published version of slice i.
+// lambda_out[i] = newest published version of slice i, capped at vcap (the
+// stopping iteration of the pipelined driver; slices ran ahead of it).
 __global__ void k_async_gather(const double *ring, const SliceHdr *hdr, double *out, long long npts, int N,
-                               int R) {
+                               int R, const int *vcap) {
     const long long all = (long long)(N + 1) * npts;
     const int i = blockIdx.y;
-    const int slot = hdr[i].ver % R;
+    const int slot = (vcap ? min(hdr[i].ver, *vcap) : hdr[i].ver) % R;
     const double *src = ring + slot * all + i * npts;
     double *dst = out + i * npts;
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += (long long)gridDim.x * blockDim.x)
