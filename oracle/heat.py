@@ -132,6 +132,33 @@ def coarse_cg(x: np.ndarray, s: float, tol: float = 1e-12, maxit: int = 0):
     return w, it
 
 
+def fine_theta(u: np.ndarray, r: float, m: int, theta: float, tol: float = 1e-12) -> np.ndarray:
+    """Implicit F: m steps of the theta-method for u_t = nu L_h u (the paper's
+    experiments use implicit fine integrators, Section 5.1: theta = 1/2 is the
+    trapezoidal rule, theta = 1 backward Euler).  Each step solves
+        (I - theta r h^2 L_h) u' = (I + (1 - theta) r h^2 L_h) u,
+    the left-hand matrix being the backward-Euler matrix with s = theta r, by
+    Thomas in 1D and by the textbook CG of coarse_cg otherwise (x0 = the
+    right-hand side, ||res||_2 <= tol ||rhs||_2)."""
+    for _ in range(m):
+        b = u + ((1.0 - theta) * r) * laplacian_h2(u) if theta != 1.0 else u
+        if u.ndim == 1:
+            u = coarse_thomas(b, theta * r)
+        else:
+            u = coarse_cg(b, theta * r, tol)[0]
+    return u
+
+
+def serial_fine_theta(u0: np.ndarray, r: float, m: int, nslices: int, theta: float,
+                      tol: float = 1e-12) -> np.ndarray:
+    """serial_fine with the implicit F of fine_theta."""
+    out = np.empty((nslices + 1,) + u0.shape)
+    out[0] = u0
+    for i in range(1, nslices + 1):
+        out[i] = fine_theta(out[i - 1], r, m, theta, tol)
+    return out
+
+
 def be_matrix(dim: int, n: int, s: float) -> np.ndarray:
     """Dense backward-Euler matrix (tiny n only), for brute-force pins."""
     N = n ** dim
@@ -160,15 +187,18 @@ class Propagators:
     """F and G bound to one discretisation (G: Thomas in 1D, CG otherwise)."""
 
     def __init__(self, disc: Discretisation, cg_tol: float = 1e-12,
-                 coarse: str = "auto"):
+                 coarse: str = "auto", theta: float = 0.0):
         self.disc = disc
         self.cg_tol = cg_tol
+        self.theta = theta      # 0: explicit Euler F; 1/2, 1: implicit F (fine_theta)
         if coarse == "auto":
             coarse = "thomas" if disc.dim == 1 else "cg"
         self.coarse = coarse
         self.cg_iters = []
 
     def F(self, u: np.ndarray) -> np.ndarray:
+        if self.theta:
+            return fine_theta(u, self.disc.r, self.disc.m, self.theta, self.cg_tol)
         return fine(u, self.disc.r, self.disc.m)
 
     def G(self, u: np.ndarray) -> np.ndarray:

@@ -86,6 +86,72 @@ def test_fine_dense_brute_force(dim, n):
     assert h2 > 0
 
 
+# ---- implicit fine propagators (theta-method: trapezoidal 1/2, backward Euler 1)
+
+def _stencil_matrix(dim, n):
+    """h^2 L_h as a dense matrix, built point by point from the stencil."""
+    N = n ** dim
+    A = np.zeros((N, N))
+    idx = np.arange(N).reshape((n,) * dim)
+    for p in range(N):
+        c = np.unravel_index(p, (n,) * dim)
+        A[p, p] = -2.0 * dim
+        for ax in range(dim):
+            for sgn in (-1, 1):
+                q = list(c)
+                q[ax] += sgn
+                if 0 <= q[ax] < n:
+                    A[p, idx[tuple(q)]] = 1.0
+    return A
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+@pytest.mark.parametrize("dim,n,kvec,r", [(1, 127, (5,), 3.0), (2, 31, (2, 7), 0.8), (3, 11, (1, 3, 9), 2.5)])
+def test_fine_theta_mode_amplification(theta, dim, n, kvec, r):
+    # on a discrete eigenmode with h^2 L_h eigenvalue -mu, one theta-step
+    # multiplies by (1 - (1 - theta) r mu) / (1 + theta r mu); unconditionally
+    # stable, so r may exceed the explicit limit 1/(2d)
+    m = 7
+    h = 1.0 / (n + 1)
+    x = np.arange(1, n + 1) * h
+    u0 = np.ones((n,) * dim)
+    mu = 0.0
+    for d, kd in enumerate(kvec):
+        shape = [1] * dim
+        shape[dim - 1 - d] = n
+        u0 = u0 * np.sin(kd * np.pi * x).reshape(shape)
+        mu += 4.0 * math.sin(kd * math.pi * h / 2) ** 2
+    amp = ((1.0 - (1.0 - theta) * r * mu) / (1.0 + theta * r * mu)) ** m
+    got = heat.fine_theta(u0, r, m, theta)
+    assert np.max(np.abs(got - amp * u0)) <= 1e-11
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+@pytest.mark.parametrize("dim,n", [(1, 9), (2, 5), (3, 3)])
+def test_fine_theta_dense_brute_force(theta, dim, n):
+    rng = np.random.default_rng(12)
+    u0 = rng.standard_normal((n,) * dim)
+    r, m = 1.7, 9
+    A = _stencil_matrix(dim, n)
+    I = np.eye(n ** dim)
+    step = np.linalg.solve(I - theta * r * A, I + (1.0 - theta) * r * A)
+    want = np.linalg.matrix_power(step, m) @ u0.ravel()
+    assert np.allclose(heat.fine_theta(u0, r, m, theta).ravel(), want, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_sync_finite_termination_implicit_fine_bitwise(theta):
+    # finite termination holds for any F (Section 3.2): with the implicit F,
+    # k = N reproduces the serial implicit integration bit for bit
+    p = workloads.heat2d(n=15, nslices=5, T=2e-2)
+    d = heat.discretise(p.dim, p.n, p.nu, p.T, p.nslices, 4 * p.dt_nominal)
+    props = heat.Propagators(d, cg_tol=1e-12, theta=theta)
+    res = parareal.parareal_sync(p.u0, props.F, props.G, d.nslices, eps=0.0)
+    ser = heat.serial_fine_theta(p.u0, d.r, d.m, d.nslices, theta)
+    assert res.iters == d.nslices
+    assert np.array_equal(res.lam, ser)
+
+
 def test_discretise_rounding_rule():
     # slice length divided into the fewest steps not above the requested one
     d = heat.discretise(2, 1024, 1.0, 1e-3, 64, 0.2 / 1025 ** 2)
