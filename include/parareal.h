@@ -54,6 +54,14 @@ extern "C" {
 #define PR_COARSE_THOMAS  1  /* 1D only */
 #define PR_COARSE_CG      2
 
+/* Fine propagator F: m steps of length dt per slice (Section 3.1 leaves F
+ * abstract; the paper's experiments use implicit schemes, Section 5.1). */
+#define PR_FINE_EXPLICIT        0  /* explicit Euler, r = nu dt/h^2 <= 1/(2d) */
+#define PR_FINE_BACKWARD_EULER  1  /* (I - r h^2 L) u' = u, any r */
+#define PR_FINE_TRAPEZOIDAL     2  /* (I - r/2 h^2 L) u' = (I + r/2 h^2 L) u, any r */
+/* Implicit steps are solved like G: Thomas (1D) or CG to cg_tol (2D/3D).  The
+ * adjoint (pr_grad) and batched handles take explicit F only. */
+
 typedef struct pr_problem pr_problem;   /* opaque, library-owned */
 
 typedef struct pr_config {
@@ -79,6 +87,7 @@ typedef struct pr_config {
     int    fine_xpts;    /* x points per lane of the fine kernel (2D/3D); 0 = default.  The
                             first shape matching every nonzero (tb_depth, tile_rows,
                             fine_xpts) is used; none matching is PR_EINVAL. */
+    int    fine;         /* PR_FINE_*: the fine propagator's time stepping */
 } pr_config;
 
 /* Derived discretisation of one problem (read-only view). */
@@ -120,6 +129,7 @@ typedef struct pr_stats {
        updates (fine propagation, predecessor copy, coarse solve, correction
        and publication) and of the whole launch; the rest is idle waiting */
     double team_fine_ms, team_copy_ms, team_coarse_ms, team_corr_ms, team_total_ms;
+    long long fine_cg_iters; /* CG iterations of implicit fine steps (2D/3D) */
 } pr_stats;
 
 /* Asynchronous-driver options (Algorithm 2 emulated by persistent teams). */

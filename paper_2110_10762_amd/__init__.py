@@ -31,6 +31,9 @@ PR_ASYNC_FREE = 0
 PR_ASYNC_EXACT = 1
 PR_ASYNC_REPLAY = 2
 PR_ASYNC_PIPELINED = 3
+PR_FINE_EXPLICIT = 0
+PR_FINE_BACKWARD_EULER = 1
+PR_FINE_TRAPEZOIDAL = 2
 
 
 class pr_config(ctypes.Structure):
@@ -40,7 +43,7 @@ class pr_config(ctypes.Structure):
         ("coarse", ctypes.c_int), ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
         ("eps", ctypes.c_double), ("kmax", ctypes.c_int), ("tb_depth", ctypes.c_int),
         ("tile_rows", ctypes.c_int), ("coarse_increment", ctypes.c_int),
-        ("fine_xpts", ctypes.c_int),
+        ("fine_xpts", ctypes.c_int), ("fine", ctypes.c_int),
     ]
 
 
@@ -70,7 +73,7 @@ class pr_stats(ctypes.Structure):
         ("idle_rounds", ctypes.c_longlong),
         ("team_fine_ms", ctypes.c_double), ("team_copy_ms", ctypes.c_double),
         ("team_coarse_ms", ctypes.c_double), ("team_corr_ms", ctypes.c_double),
-        ("team_total_ms", ctypes.c_double),
+        ("team_total_ms", ctypes.c_double), ("fine_cg_iters", ctypes.c_longlong),
     ]
 
 
@@ -154,9 +157,9 @@ def _ptr(x) -> int:
 
 def make_config(dim, n, nu, T, nslices, dt_nominal, coarse=PR_COARSE_AUTO, cg_tol=1e-12,
                 cg_maxit=0, eps=1e-10, kmax=0, tb_depth=0, tile_rows=0,
-                coarse_increment=0, fine_xpts=0) -> pr_config:
+                coarse_increment=0, fine_xpts=0, fine=0) -> pr_config:
     return pr_config(dim, n, nu, T, nslices, dt_nominal, coarse, cg_tol, cg_maxit, eps, kmax,
-                     tb_depth, tile_rows, coarse_increment, fine_xpts)
+                     tb_depth, tile_rows, coarse_increment, fine_xpts, fine)
 
 
 def config_of(problem, **over) -> pr_config:

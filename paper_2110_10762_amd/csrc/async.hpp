@@ -38,6 +38,7 @@
 #pragma once
 #include "fine.hpp"
 #include "coarse.hpp"
+#include "implicit.hpp"
 
 namespace pr {
 
@@ -78,7 +79,7 @@ struct AsyncWork {
     unsigned *tctr = nullptr;
     long long *tbc = nullptr;
     double *tred = nullptr;
-    double *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr;
+    double *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr, *cgb = nullptr;
     unsigned long long *counters = nullptr;
     unsigned long long *pub_t = nullptr;   // [(N+1) R] publication time of each slot's version
     int *pipe = nullptr;                   // PIPELINED: [N+2] publications per version, then K*
@@ -110,6 +111,9 @@ struct AsyncArgs {
     unsigned long long *pipe_dmax;  // PIPELINED: [N+1] max change of each version (bits)
     int kcap;                     // PIPELINED: iteration cap (k = N is exact)
     int blocks;                   // slices per team: contiguous blocks (1) or every nteams-th (0)
+    int fine_kind;                // FINE_EXPLICIT or an implicit theta-method
+    const double *inv_tab_f;      // 1D implicit fine steps: Thomas factors of s = theta r
+    double *cgb;                  // implicit trapezoidal fine steps: [nteams * cgs] right-hand sides
     int nteams, maxtsz;
     const int *team_of, *rank_of, *tsize;   // per workgroup / per team
     unsigned *tctr;          // [nteams * 16]
@@ -241,8 +245,30 @@ __device__ __forceinline__ void team_copy(const Team &tm, const Geom &g, const d
 }
 
 // ---- fine propagation of one state by a team: passes of <= D steps
-template <int DIM, int XP, int RR, int D>
-__device__ bool team_fine(Team &tm, const AsyncArgs &a, const double *src, double *dst, double *scr) {
+// IMPL: the implicit fine propagators (a separate instantiation, so that the
+// explicit kernel carries none of their registers).
+template <int DIM, int XP, int RR, int D, bool IMPL>
+__device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const double *src, double *dst, double *scr,
+                          const CGWork &wk, double *rhs, unsigned long long &fine_its) {
+    if constexpr (IMPL) {   // implicit theta-steps: Thomas per wave (1D), team CG
+        if constexpr (DIM == 1) {
+            if (wave_id() == 0) {
+                const double th = theta_of(a.fine_kind);
+                double c[RR], rl[RR], inv[RR];
+                load1d<RR>(src, a.n, (1.0 - th) * a.r, c, rl);
+                load_inv<RR>(a.inv_tab_f, inv);
+                fine1d_theta_regs<RR>(c, rl, inv, a.n, th * a.r, a.m, a.fine_kind == FINE_TRAPEZOIDAL);
+                store1d<RR>(dst, a.n, c);
+            }
+            return team_sync(tm);
+        } else {
+            const long long it = team_fine_theta<DIM, 1>(tm, a.g, a.fine_kind, a.r, a.m, a.cg_tol, a.cg_maxit,
+                                                          src, dst, scr, rhs, wk);
+            if (it < 0) return false;
+            fine_its += (unsigned long long)it;
+            return true;
+        }
+    }
     if constexpr (DIM == 1) {
         if (wave_id() == 0) {
             double c[RR], rl[RR];
@@ -328,7 +354,7 @@ enum { ACT_IDLE = 0, ACT_UPDATE = 1, ACT_DONE = 2 };
 // The arguments live in device memory: read through a uniform pointer they
 // stay in scalar registers, where a by-value struct passed on by reference
 // would be copied to scratch.
-template <int DIM, int XP, int RR, int D>
+template <int DIM, int XP, int RR, int D, bool IMPL = false>
 __global__ __launch_bounds__(BLOCK, DIM == 2 ? 3 : (DIM == 3 ? 2 : 1)) void k_async(const AsyncArgs *__restrict__ ap) {
     const AsyncArgs &a = *ap;
     const int team = a.team_of[blockIdx.x];
@@ -345,7 +371,7 @@ __global__ __launch_bounds__(BLOCK, DIM == 2 ? 3 : (DIM == 3 ? 2 : 1)) void k_as
     const long long np = a.npts;
     const long long all = (long long)(a.N + 1) * np;
     const unsigned long long t0 = wall_clock64();
-    unsigned long long cg_its = 0, g_solves = 0, g_skips = 0, retries = 0, idles = 0;
+    unsigned long long cg_its = 0, g_solves = 0, g_skips = 0, retries = 0, idles = 0, fine_its = 0;
     // wall-clock ticks the team spends per phase (leader's view)
     unsigned long long t_fine = 0, t_copy = 0, t_coarse = 0, t_corr = 0, tp = 0;
 
@@ -457,7 +483,9 @@ __global__ __launch_bounds__(BLOCK, DIM == 2 ? 3 : (DIM == 3 ? 2 : 1)) void k_as
             double *v = a.V + i * np;
             // ---------------- v = F(x_old)
             tp = wall_clock64();
-            if (!team_fine<DIM, XP, RR, D>(tm, a, x_old, v, a.S ? a.S + i * np : nullptr)) goto out;
+            if (!team_fine<DIM, XP, RR, D, IMPL>(tm, a, x_old, v, a.S ? a.S + i * np : nullptr, wk,
+                                           a.cgb ? a.cgb + (long long)team * a.cgs : nullptr, fine_its))
+                goto out;
             {   // uniform code: the phase clocks stay in scalar registers
                 const unsigned long long t = wall_clock64();
                 t_fine += t - tp;
@@ -529,14 +557,14 @@ __global__ __launch_bounds__(BLOCK, DIM == 2 ? 3 : (DIM == 3 ? 2 : 1)) void k_as
             }
             const double *wv = w_old;
             if (!stale) {
-                int it;
+                // one call site: the kernel holds a single copy of the solver
+                double thr = -1.0;
                 if (a.incr) {
                     double nrm = 0.0;
                     if (!team_reduce<false>(tm, nrm_part, wk.red, nrm, lds)) goto out;
-                    it = team_coarse<DIM, RR>(tm, a, dbuf, ybuf, wk, a.cg_tol * a.cg_tol * nrm);
-                } else {
-                    it = team_coarse<DIM, RR>(tm, a, x_new, w_new, wk);
+                    thr = a.cg_tol * a.cg_tol * nrm;
                 }
+                const int it = team_coarse<DIM, RR>(tm, a, a.incr ? dbuf : x_new, a.incr ? ybuf : w_new, wk, thr);
                 if (it < 0) goto out;
                 cg_its += (unsigned long long)it;
                 ++g_solves;
@@ -639,6 +667,7 @@ out:
         __hip_atomic_fetch_add(&a.counters[7], t_coarse, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&a.counters[8], t_corr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&a.counters[9], wall_clock64() - t0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.counters[10], fine_its, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

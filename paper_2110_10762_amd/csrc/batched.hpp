@@ -144,7 +144,7 @@ __global__ __launch_bounds__(BLOCK) void k_bsweep(BatchArgs a) {
         unsigned long long its = 0;
         const SweepBufs SB{a.lam + P.off_lam, a.v + P.off_lam, a.w + P.off_lam, wn,
                            a.d0 + team * a.maxnpts, a.d1 + team * a.maxnpts};
-        if (!team_coarse_sweep(tm, P.g, P.s, P.cg_tol, P.cg_maxit, P.npts, init ? 1 : k, P.N, init ? -1 : k, init,
+        if (!team_coarse_sweep<2>(tm, P.g, P.s, P.cg_tol, P.cg_maxit, P.npts, init ? 1 : k, P.N, init ? -1 : k, init,
                                P.incr != 0, SB, wk, dmax, its, lds))
             return;
         double delta = 0.0;

@@ -21,6 +21,7 @@
 #include "async.hpp"
 #include "adjoint.hpp"
 #include "batched.hpp"
+#include "implicit.hpp"
 
 using namespace pr;
 
@@ -98,6 +99,7 @@ struct Prob {
     double cg_tol;
     int cg_maxit, kmax;
     double eps;
+    int fine;              // FINE_EXPLICIT, FINE_BACKWARD_EULER or FINE_TRAPEZOIDAL
 };
 
 struct Buf {
@@ -115,6 +117,12 @@ struct pr_problem {
     double *v = nullptr, *w = nullptr, *tmp = nullptr, *wn = nullptr, *d0 = nullptr, *d1 = nullptr;
     double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *red = nullptr;
     double *inv_tab = nullptr;        // 1D Thomas factors, padded
+    double *inv_tab_f = nullptr;      // 1D Thomas factors of an implicit fine step (s = theta r)
+    // implicit fine steps on many states (2D/3D): per-team tmp, rhs, CG set
+    double *fth_scr = nullptr, *fth_red = nullptr;
+    unsigned *fth_ctr = nullptr;
+    unsigned long long *fth_its = nullptr;
+    int fth_grid = 0;
     unsigned *ctr = nullptr;          // team barrier counters
     Control *ctl = nullptr;
     double *dscal = nullptr;          // device scalars: [0] delta
@@ -183,6 +191,7 @@ static int derive(const pr_config &c, Prob &P) {
     if (c.coarse == PR_COARSE_CG && c.dim == 1)
         return fail(PR_EINVAL, "1D problems use the Thomas coarse solver");
     if (c.coarse < 0 || c.coarse > 2) return fail(PR_EINVAL, "unknown coarse solver %d", c.coarse);
+    if (c.fine < PR_FINE_EXPLICIT || c.fine > PR_FINE_TRAPEZOIDAL) return fail(PR_EINVAL, "unknown fine propagator %d", c.fine);
     P.cfg = c;
     P.dim = c.dim;
     P.n = c.n;
@@ -197,7 +206,8 @@ static int derive(const pr_config &c, Prob &P) {
     P.dt = P.dT / P.m;
     P.r = P.nu * P.dt / (P.h * P.h);
     P.s = P.nu * P.dT / (P.h * P.h);
-    if (P.r > 0.5 / P.dim * (1.0 + 1e-12))
+    P.fine = c.fine;
+    if (P.fine == FINE_EXPLICIT && P.r > 0.5 / P.dim * (1.0 + 1e-12))
         return fail(PR_EUNSTABLE, "explicit Euler unstable: r = %.6g > 1/(2d) = %.6g", P.r, 0.5 / P.dim);
     P.g = make_geom(P.dim, P.n);
     P.npts = P.g.npts;
@@ -322,9 +332,13 @@ static int fine_depth(const Prob &P) {
 
 // Passes of at most D steps; the passes ping-pong between dst and tmp so that
 // the last one lands in dst.  src is never written.
+static int run_fine_theta(pr_problem *h, const Prob &P, const double *src, double *dst, int count, int steps,
+                          long long ss, long long ds);
+
 static int run_fine(pr_problem *h, const Prob &P, const double *src, double *dst, double *tmp, int count,
                     int steps, long long ss, long long ds) {
     if (count <= 0 || steps <= 0) return PR_OK;
+    if (P.fine != FINE_EXPLICIT) return run_fine_theta(h, P, src, dst, count, steps, ss, ds);
     if (P.dim == 1) {
         launch1d(h->stream, src, dst, ss, ds, P.n, P.r, steps, count);
         HIPCHK(hipGetLastError());
@@ -386,6 +400,74 @@ static int check_control(pr_problem *h) {
     return PR_OK;
 }
 
+static int thomas_table(pr_problem *h, int n, double s, double **tab);
+
+// Implicit fine steps (theta-method) of `count` states: 1D one wave per state
+// in registers; 2D/3D a cooperative launch of teams, one per XCD (fewer when
+// there are fewer states), each with its own tmp, rhs and CG set.  The CG
+// iterations accumulate in h->fth_its.
+static int run_fine_theta(pr_problem *h, const Prob &P, const double *src, double *dst, int count, int steps,
+                          long long ss, long long ds) {
+    int rc;
+    if (P.dim == 1) {
+        if (!h->inv_tab_f && (rc = thomas_table(h, P.n, theta_of(P.fine) * P.r, &h->inv_tab_f))) return rc;
+        const int R = r1d_for(P.n);
+#define F1(RR)                                                                                                  \
+    hipLaunchKernelGGL((k_fine1d_theta<RR>), dim3(count), dim3(64), 0, h->stream, src, dst, ss, ds, P.n, P.r, \
+                       P.fine, h->inv_tab_f, steps, count)
+        switch (R) {
+            case 1: F1(1); break;
+            case 2: F1(2); break;
+            case 4: F1(4); break;
+            case 8: F1(8); break;
+            case 16: F1(16); break;
+            default: F1(32); break;
+        }
+#undef F1
+        HIPCHK(hipGetLastError());
+        return PR_OK;
+    }
+    const void *fn = P.dim == 2 ? (const void *)k_fine_theta<2> : (const void *)k_fine_theta<3>;
+    const long long stride = (P.npts + 63) / 64 * 64 + 1536;   // per-team vectors, staggered in memory
+    if (!h->fth_scr) {
+        int occ = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, BLOCK, 0));
+        if (occ < 1) return fail(PR_ENORESIDENT, "implicit fine kernel cannot be resident");
+        h->fth_grid = (h->ncu * std::min(occ, 4)) / kXcds * kXcds;
+        if ((rc = alloc_t(h, &h->fth_scr, (size_t)kXcds * 5 * stride))) return rc;
+        if ((rc = alloc_t(h, &h->fth_red, (size_t)2 * h->fth_grid))) return rc;
+        if ((rc = alloc_t(h, &h->fth_ctr, (size_t)kXcds * team_counter_words(0)))) return rc;
+        if ((rc = alloc_t(h, &h->fth_its, 1))) return rc;
+        if ((rc = zero_words(h, h->fth_its, 2))) return rc;
+    }
+    int nteams = 1;
+    while (nteams * 2 <= std::min(count, kXcds)) nteams *= 2;
+    if ((rc = zero_words(h, h->fth_ctr, kXcds * team_counter_words(0)))) return rc;
+    if ((rc = zero_words(h, h->ctl, sizeof(Control) / 4))) return rc;
+    Geom g = P.g;
+    int kind = P.fine, maxit = P.cg_maxit;
+    double r = P.r, tol = P.cg_tol;
+    double *scr = h->fth_scr, *red = h->fth_red;
+    unsigned *ctr = h->fth_ctr;
+    Control *ctl = h->ctl;
+    unsigned long long *its = h->fth_its;
+    long long strd = stride;
+    void *args[] = {&src, &dst, &ss, &ds, &count, &g, &kind, &r, &steps, &tol, &maxit, &scr, &strd, &ctr, &red,
+                    &ctl, &nteams, &its};
+    if ((rc = coop_launch(h, fn, h->fth_grid, BLOCK, args))) return rc;
+    return check_control(h);
+}
+
+static int reset_fine_its(pr_problem *h) {
+    return h->fth_its ? zero_words(h, h->fth_its, 2) : PR_OK;
+}
+
+static long long read_fine_its(pr_problem *h) {
+    unsigned long long v = 0;
+    if (h->fth_its && hipMemcpy(&v, h->fth_its, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    return (long long)v;
+}
+
 static SweepArgs sweep_args(pr_problem *h, const Prob &P, double *lam) {
     SweepArgs a{};
     a.lam = lam;
@@ -432,7 +514,8 @@ static int run_sweep(pr_problem *h, const Prob &P, SweepArgs a) {
     rc = zero_words(h, h->ctl, sizeof(Control) / 4);
     if (rc) return rc;
     void *args[] = {&a};
-    return coop_launch(h, (const void *)k_sweep_cg, h->sweep_grid, SWEEP_BLOCK, args);
+    const void *fn = P.dim == 3 ? (const void *)k_sweep_cg<3> : (const void *)k_sweep_cg<2>;
+    return coop_launch(h, fn, h->sweep_grid, SWEEP_BLOCK, args);
 }
 
 // ------------------------------------------------------------------ create / destroy
@@ -456,19 +539,27 @@ static int alloc_sync(pr_problem *h) {
     return PR_OK;
 }
 
+// Thomas elimination factors of tridiag(-s, 1+2s, -s), padded to 64*R:
+// inv_i = 1 / (1 + 2s + s c'_{i-1}), c'_i = -s inv_i, c'_{-1} = 0.
+static int thomas_table(pr_problem *h, int n, double s, double **tab) {
+    const int R = r1d_for(n);
+    std::vector<double> inv(WAVE * R, 0.0);
+    double cprev = 0.0;
+    for (int i = 0; i < n; ++i) {
+        inv[i] = 1.0 / (1.0 + 2.0 * s + s * cprev);
+        cprev = -s * inv[i];
+    }
+    int rc = alloc_t(h, tab, inv.size());
+    if (rc) return rc;
+    HIPCHK(hipMemcpy(*tab, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice));
+    return PR_OK;
+}
+
 static int setup_1d(pr_problem *h) {
     const Prob &P = h->P[0];
-    const int R = r1d_for(P.n);
-    std::vector<double> inv(WAVE * R, 0.0);
-    // inv_i = 1 / (1 + 2s + s c'_{i-1}), c'_i = -s inv_i, c'_{-1} = 0
-    double cprev = 0.0;
-    for (int i = 0; i < P.n; ++i) {
-        inv[i] = 1.0 / (1.0 + 2.0 * P.s + P.s * cprev);
-        cprev = -P.s * inv[i];
-    }
-    int rc = alloc_t(h, &h->inv_tab, inv.size());
+    int rc = thomas_table(h, P.n, P.s, &h->inv_tab);
     if (rc) return rc;
-    HIPCHK(hipMemcpy(h->inv_tab, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (P.fine != FINE_EXPLICIT) return thomas_table(h, P.n, theta_of(P.fine) * P.r, &h->inv_tab_f);
     return PR_OK;
 }
 
@@ -500,6 +591,8 @@ extern "C" int pr_create(const pr_config *cfgs, int nproblems, int device, void 
             return bail(fail(rc, "config %d: %s", b, m.c_str()));
         }
         if (nproblems > 1 && P.dim != 2) return bail(fail(PR_EINVAL, "batched problems must be 2D"));
+        if (nproblems > 1 && P.fine != FINE_EXPLICIT)
+            return bail(fail(PR_EINVAL, "batched problems take the explicit fine propagator"));
         P.off_state = off_s;
         P.off_lam = off_l;
         off_s += P.npts;
@@ -514,7 +607,10 @@ extern "C" int pr_create(const pr_config *cfgs, int nproblems, int device, void 
     if ((rc = alloc_t(h, &h->dscal, 16))) return bail(rc);
     if ((rc = alloc_t(h, &h->iscal, 16))) return bail(rc);
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_sweep_cg, SWEEP_BLOCK, 0) != hipSuccess || occ < 1)
+    int occ2 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_sweep_cg<3>, SWEEP_BLOCK, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, (const void *)k_sweep_cg<2>, SWEEP_BLOCK, 0) != hipSuccess ||
+        std::min(occ, occ2) < 1)
         return bail(fail(PR_EHIP, "occupancy query failed"));
     h->sweep_grid = h->ncu * std::min(occ, 1);
     h->red_slots = 2 * 4096;
@@ -635,6 +731,7 @@ static void stats_reset(pr_stats *st) {
     st->kernel_cg_iters = st->kernel_updates = 0;
     st->copy_retries = st->idle_rounds = 0;
     st->team_fine_ms = st->team_copy_ms = st->team_coarse_ms = st->team_corr_ms = st->team_total_ms = 0;
+    st->fine_cg_iters = 0;
 }
 
 // ------------------------------------------------------------------ apply entry points
@@ -691,7 +788,8 @@ extern "C" int pr_apply_coarse(pr_problem *h, const double *in, double *out, int
     Control *ctl = h->ctl;
     unsigned long long *ci = h->iscal;
     void *args[] = {&in, &out, &npts, &count, &g, &s, &tol, &maxit, &wk, &ctr, &ctl, &ci};
-    if ((rc = coop_launch(h, (const void *)k_coarse_cg_batch, h->sweep_grid, SWEEP_BLOCK, args))) return rc;
+    const void *fn = P.dim == 3 ? (const void *)k_coarse_cg_batch<3> : (const void *)k_coarse_cg_batch<2>;
+    if ((rc = coop_launch(h, fn, h->sweep_grid, SWEEP_BLOCK, args))) return rc;
     if ((rc = check_control(h))) return rc;
     unsigned long long its = 0;
     HIPCHK(hipMemcpy(&its, h->iscal, sizeof its, hipMemcpyDeviceToHost));
@@ -706,6 +804,7 @@ extern "C" int pr_solve_fine(pr_problem *h, const double *u0, double *lam, pr_st
     const Prob &P = h->P[0];
     if (!u0 || !lam) return fail(PR_EINVAL, "NULL buffer");
     stats_reset(st);
+    if ((rc = reset_fine_its(h))) return rc;
     HIPCHK(hipEventRecord(h->ev[0], h->stream));
     if ((rc = copy_dev(h, u0, lam, P.npts))) return rc;
     Prob P1 = P;   // single-state runs may use their own tuned shape
@@ -723,6 +822,7 @@ extern "C" int pr_solve_fine(pr_problem *h, const double *u0, double *lam, pr_st
         st->wall_ms = st->fine_ms = elapsed(h->ev[0], h->ev[1]);
         st->fine_lups = (double)P.N * P.m * (double)P.npts;
         st->converged = 1;
+        st->fine_cg_iters = read_fine_its(h);
     }
     return PR_OK;
 }
@@ -740,6 +840,7 @@ extern "C" int pr_solve_sync(pr_problem *h, const double *u0, double *lam, pr_st
     if (!h->v) return fail(PR_EINVAL, "synchronous workspace missing");
     stats_reset(st);
     const long long np = P.npts;
+    if ((rc = reset_fine_its(h))) return rc;
     HIPCHK(hipEventRecord(h->ev[0], h->stream));
     if ((rc = copy_dev(h, u0, lam, np))) return rc;
     if ((rc = zero_words(h, h->iscal, 2))) return rc;
@@ -805,6 +906,7 @@ extern "C" int pr_solve_sync(pr_problem *h, const double *u0, double *lam, pr_st
         st->cg_iters = (long long)its;
         st->g_solves = gs;
         st->g_skipped = gskip;
+        st->fine_cg_iters = read_fine_its(h);
     }
     if (!conv && P.eps > 0) return fail(PR_ENOTCONV, "kmax = %d reached with delta = %.3e", P.kmax, delta);
     return PR_OK;

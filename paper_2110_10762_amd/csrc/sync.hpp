@@ -114,6 +114,7 @@ struct SweepBufs {
     double *w, *wn, *d0, *d1;
 };
 
+template <int DIM>
 __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol, int maxit, long long npts,
                                   int i0, int i1, int kguard, bool init, bool incr, const SweepBufs &B,
                                   const CGWork &wk, double &dmax, unsigned long long &its, double *lds) {
@@ -129,8 +130,10 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
         double *wi = B.w + (long long)i * npts;
         const double *vi = B.v + (long long)i * npts;
         if (!skip) {
-            const int it = incr ? cg_team(tm, g, s, tol, maxit, dprev, B.wn, wk, tol * tol * nrm_prev)
-                                : cg_team(tm, g, s, tol, maxit, B.lam + (long long)(i - 1) * npts, B.wn, wk);
+            // one call site: the kernel holds a single copy of the solver
+            const int it = cg_team_dim<DIM, DIM == 3 ? 1 : 2>(tm, g, s, tol, maxit,
+                                                              incr ? dprev : B.lam + (long long)(i - 1) * npts,
+                                                              B.wn, wk, incr ? tol * tol * nrm_prev : -1.0);
             if (it < 0) return false;
             its += (unsigned long long)it;
         }
@@ -171,6 +174,8 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
 }
 
 // Cooperative launch: the whole grid is one team.
+// one instantiation per dimension (2, 3): each kernel holds one solver copy
+template <int DIM>
 __global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
     Team tm{a.ctr, a.ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
     if (!team_setup(tm)) return;
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
     double dmax = 0.0;
     unsigned long long its = 0;
     const SweepBufs B{a.lam, a.v, a.w, a.wn, a.d0, a.d1};
-    if (!team_coarse_sweep(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
+    if (!team_coarse_sweep<DIM>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
                            a.incr != 0, B, a.wk, dmax, its, lds))
         return;
     dmax = block_reduce<true>(dmax, lds);
@@ -191,6 +196,7 @@ __global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
 
 // Batch of independent coarse solves (tests and the apply entry point):
 // state c of the batch is solved by the whole grid, one after the other.
+template <int DIM>
 __global__ __launch_bounds__(1024) void k_coarse_cg_batch(const double *src, double *dst, long long npts,
                                                            int count, Geom g, double s, double tol,
                                                            int maxit, CGWork wk, unsigned *ctr,
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(1024) void k_coarse_cg_batch(const double *src, dou
     if (!team_setup(tm)) return;
     unsigned long long its = 0;
     for (int c = 0; c < count; ++c) {
-        const int it = cg_team(tm, g, s, tol, maxit, src + c * npts, dst + c * npts, wk);
+        const int it = cg_team_dim<DIM, DIM == 3 ? 1 : 2>(tm, g, s, tol, maxit, src + c * npts, dst + c * npts, wk, -1.0);
         if (it < 0) return;
         its += (unsigned long long)it;
         if (!team_sync(tm)) return;
