@@ -293,7 +293,7 @@ __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const do
                         const int ya = (sidx % a.nsy) * RR;
                         // two rows in flight: this persistent kernel's occupancy is set by
                         // its registers, and CG, not F, dominates its time
-                        fine2d_sw<XP, D, 2>(cur, tgt, a.n, a.r, st, sidx / a.nsy, ya, min(a.n, ya + RR),
+                        fine2d_sw<XP, D, 2, false>(cur, tgt, a.n, a.r, st, sidx / a.nsy, ya, min(a.n, ya + RR),
                                          (sidx % a.nsy) & 1);
                     } else {
                         fine2d_strip<XP, RR, D>(cur, tgt, a.n, a.r, st, sidx / a.nsy, sidx % a.nsy);

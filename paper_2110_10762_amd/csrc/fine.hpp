@@ -213,12 +213,23 @@ __device__ __forceinline__ int reflect_row(int y, int n, double &ys) {
 }
 
 // Issues the loads of row yi (no wait: the values are used PF rows later).
-template <int XP>
+// VEC: the lane's XP points are contiguous and 16-byte aligned (an interior
+// strip, XP even): XP/2 16-byte loads, so each instruction moves whole lines.
+template <int XP, bool VEC>
 __device__ __forceinline__ void issue_row2d(const double *__restrict__ src, int n, int yi, const unsigned (&xo)[XP],
                                             double (&v)[XP]) {
     const char *row = reinterpret_cast<const char *>(src + (long long)yi * n);
+    if constexpr (VEC) {
 #pragma unroll
-    for (int e = 0; e < XP; ++e) v[e] = *reinterpret_cast<const double *>(row + xo[e]);
+        for (int e = 0; e < XP; e += 2) {
+            const double2 t = *reinterpret_cast<const double2 *>(row + xo[e]);
+            v[e] = t.x;
+            v[e + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < XP; ++e) v[e] = *reinterpret_cast<const double *>(row + xo[e]);
+    }
 }
 
 template <int XP, int D>
@@ -229,9 +240,9 @@ struct ShapeSW {
 
 // PF: input rows in flight ahead of the window (more hides HBM latency, fewer
 // saves registers).
-template <int XP, int D, int PF = ShapeSW<XP, D>::PF>
-__device__ __forceinline__ void fine2d_sw(const double *__restrict__ src, double *__restrict__ dst, int n,
-                                          double r, int steps, int sx, int ya, int yb, bool upward) {
+template <int XP, int D, int PF, bool VEC>
+__device__ __forceinline__ void fine2d_sw_body(const double *__restrict__ src, double *__restrict__ dst, int n,
+                                               double r, int steps, int sx, int ya, int yb, bool upward) {
     constexpr int W = ShapeSW<XP, D>::W;
     const int lane = threadIdx.x & (WAVE - 1);
     const int x0 = sx * W - D;
@@ -261,7 +272,7 @@ __device__ __forceinline__ void fine2d_sw(const double *__restrict__ src, double
     for (int q = 0; q < PF; ++q) {
         const int yi = reflect_row(first + dir * q, n, ps[q]);
         if (q < nrows) {
-            issue_row2d<XP>(src, n, yi, xo, pf[q]);
+            issue_row2d<XP, VEC>(src, n, yi, xo, pf[q]);
         } else {
 #pragma unroll
             for (int e = 0; e < XP; ++e) pf[q][e] = 0.0;
@@ -276,7 +287,7 @@ __device__ __forceinline__ void fine2d_sw(const double *__restrict__ src, double
             for (int e = 0; e < XP; ++e) c[e] = (ps[q] * xs[e]) * pf[q][e];
             if (k + PF < nrows) {
                 const int yi = reflect_row(first + dir * (k + PF), n, ps[q]);
-                issue_row2d<XP>(src, n, yi, xo, pf[q]);
+                issue_row2d<XP, VEC>(src, n, yi, xo, pf[q]);
             }
 #pragma unroll
             for (int t = 0; t < D; ++t) {
@@ -293,16 +304,39 @@ __device__ __forceinline__ void fine2d_sw(const double *__restrict__ src, double
             const int y = first + dir * (k - D);
             if (k < nrows && y >= ya && y < yb) {
                 double *row = dst + (long long)y * n;
+                if constexpr (VEC) {   // owned points come in aligned pairs here
 #pragma unroll
-                for (int e = 0; e < XP; ++e)
-                    if (own[e]) row[x0 + lane * XP + e] = c[e];
+                    for (int e = 0; e < XP; e += 2)
+                        if (own[e]) *reinterpret_cast<double2 *>(row + x0 + lane * XP + e) = make_double2(c[e], c[e + 1]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < XP; ++e)
+                        if (own[e]) row[x0 + lane * XP + e] = c[e];
+                }
             }
         }
     }
 }
 
-// Output rows [sy*ry, sy*ry + ry) of strip sx; vertical neighbours are
-// consecutive waves.
+// A strip wholly inside the grid with XP even, n even and the halo even reads
+// and writes 16-byte pairs; every other strip goes through the reflection.
+// (VEC_OK = false keeps a single copy of the body, for kernels whose size or
+// registers matter more than the fine pass.)
+template <int XP, int D, int PF = ShapeSW<XP, D>::PF, bool VEC_OK = true>
+__device__ __forceinline__ void fine2d_sw(const double *__restrict__ src, double *__restrict__ dst, int n,
+                                          double r, int steps, int sx, int ya, int yb, bool upward) {
+    constexpr int W = ShapeSW<XP, D>::W;
+    const int x0 = sx * W - D;
+    if constexpr (VEC_OK && XP % 2 == 0 && D % 2 == 0) {
+        if (x0 >= 0 && x0 + WAVE * XP <= n && (n & 1) == 0) {
+            fine2d_sw_body<XP, D, PF, true>(src, dst, n, r, steps, sx, ya, yb, upward);
+            return;
+        }
+    }
+    fine2d_sw_body<XP, D, PF, false>(src, dst, n, r, steps, sx, ya, yb, upward);
+}
+
+// Output rows [sy*ry, sy*ry + ry) of strip sx.
 template <int XP, int D>
 __global__ __launch_bounds__(BLOCK) void k_fine2d_sw(const double *__restrict__ src, double *__restrict__ dst,
                                                      long long sstride, long long dstride, int n, double r,
@@ -314,8 +348,8 @@ __global__ __launch_bounds__(BLOCK) void k_fine2d_sw(const double *__restrict__ 
     if (wv >= per_state * count) return;
     const int st = (int)(wv / per_state);
     const int rem = (int)(wv - (long long)st * per_state);
-    const int sy = rem % nsy;
-    const int sx = rem / nsy;
+    const int sx = rem % nsx;   // strips of the same rows side by side: adjacent memory in flight
+    const int sy = rem / nsx;
     const int ya = sy * ry;
     fine2d_sw<XP, D>(src + st * sstride, dst + st * dstride, n, r, steps, sx, ya, min(n, ya + ry), sy & 1);
 }
