@@ -166,9 +166,12 @@ def main():
     value = lups / wall / 1e9
 
     # ---- roofline objects (algorithmic bytes per launch / live event durations)
-    # Algorithmic bytes per point: F pass 16 (read + write the state); CG
+    # Algorithmic bytes per point: F pass 16 (read + write the state).
+    # Whole-GPU sweep CG (one synchronisation per iteration): iteration 80
+    # (reads r, w, s_old, p_old, x; writes s, p, x, r', w'), set-up 40 (read
+    # b, write x, r0; read r0, write w0).  Team CG of the async kernel:
     # iteration 64 (phase A reads r, p_old, writes p; phase B reads p, x, r,
-    # writes x, r); CG set-up 24 (read b, write x, r); correction 48 (read v,
+    # writes x, r), set-up 24 (read b, write x, r).  Correction 48 (read v,
     # w_new, w_old, lambda_old, write lambda, w).
     D = info.tb_depth
     passes = -(-m // D)
@@ -184,7 +187,7 @@ def main():
                       "launches": f_launches, "avg_launch_ms": f_ms / f_launches,
                       "glups": sum(x["fine_lups"] for x in s) / (f_ms * 1e-3) / 1e9}
         c_ms = sum(x["coarse_ms"] for x in s)
-        c_bytes = sum(x["cg_iters"] * 64.0 * npts + x["g_solves"] * 24.0 * npts
+        c_bytes = sum(x["cg_iters"] * 80.0 * npts + x["g_solves"] * 40.0 * npts
                       + (x["g_solves"] + x["g_skipped"]) * 48.0 * npts for x in s)
         c_launches = sum(x["iters"] + 1 for x in s)
         rl["sweep"] = {"kernel": "k_sweep_cg", "bound": "hbm", "achieved": c_bytes / (c_ms * 1e-3) / 1e9,

@@ -6,10 +6,13 @@
 //       two first-order affine recurrences and evaluated by one wave with a
 //       log-depth lane scan (the elimination factors are the same for every
 //       slice and iteration and are precomputed once on the host).
-//   2D/3D: textbook conjugate gradients started from x0 = b, stopped at
+//   2D/3D: conjugate gradients started from x0 = b, stopped at
 //       ||r||_2 <= tol ||b||_2, executed by a team of workgroups with
-//       deterministic team reductions (two team barriers per iteration: the
-//       search-direction update is fused into the matrix-vector product).
+//       deterministic team reductions.  Teams inside one XCD run the textbook
+//       recurrences (two team barriers per iteration: the search-direction
+//       update is fused into the matrix-vector product); whole-GPU teams,
+//       whose barriers cross the XCDs, run the Chronopoulos-Gear variant with
+//       one barrier per iteration.
 #pragma once
 #include "common.hpp"
 
@@ -411,6 +414,119 @@ __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int ma
         pold = pcur;
         pcur = (pcur == wk.p0) ? wk.p1 : wk.p0;
         ++it;
+    }
+    return it;
+}
+
+// ------------------------------------------------------------------ CG, one synchronisation per iteration
+// The Chronopoulos-Gear form of CG: with w = A r and s = A p carried by
+// recurrences, both inner products of an iteration, (r, r) and (w, r), are
+// reduced together, so an iteration costs one team barrier instead of two.
+// The residual update r' = r - alpha (w + beta s_old) is fused into the next
+// product w' = A r' by recomputing r' at the neighbours from the stored r, w
+// and s_old (identical arithmetic everywhere, so every copy agrees bit for
+// bit); r, w and s are double-buffered because neighbours read the old ones
+// while the new ones are written.  80 B of HBM traffic per point and
+// iteration (reads r, w, s_old, p_old, x; writes s, p, x, r', w').  Same
+// start and stop rules as cg_team_dim; the iterates agree with it up to
+// rounding.  For whole-GPU teams, whose barriers span the XCDs.
+struct CGWork1 {
+    double *r[2], *w[2], *s[2], *p;   // [npts] each
+    double *red;                      // [4 * team size] reduction slots
+};
+
+template <int DIM>
+__device__ int cg_team_sync1(Team &tm, const Geom &g, double s, double tol, int maxit,
+                             const double *__restrict__ b, double *__restrict__ x, const CGWork1 &wk,
+                             double abs_thresh2) {
+    constexpr int V = 2 * DIM;
+    __shared__ double lds[MAX_WAVES];
+    const double twod = 2.0 * DIM;
+    const int n = g.n;
+    const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
+    const int wv = wave_id();
+    const long long nw = nwaves();
+    const bool from_zero = abs_thresh2 >= 0.0;
+    int cur = 0;
+
+    // r0 = b - A x0, x = x0 (x0 = b, or 0 for a change of the input)
+    double bb_p = 0.0;
+    for (long long c = cr.begin + wv; c < cr.end; c += nw) {
+        const CPt q = cpt_at(g, c);
+        double v[V];
+        cpt_load<DIM>(q, n, [&](int j) { return b[j]; }, v);
+        double bv;
+        const double ab = cpt_apply<DIM>(q, v, bv, twod, s);
+        if (q.m & CP_VALID) {
+            x[q.c] = from_zero ? 0.0 : bv;
+            wk.r[0][q.c] = from_zero ? bv : bv - ab;
+            bb_p = __builtin_fma(bv, bv, bb_p);
+        }
+    }
+    double bb, unused;
+    if (!team_reduce2(tm, bb_p, 0.0, wk.red, bb, unused, lds)) return -1;
+    // w0 = A r0, gamma = (r0, r0), delta = (w0, r0)
+    double ga_p = 0.0, de_p = 0.0;
+    for (long long c = cr.begin + wv; c < cr.end; c += nw) {
+        const CPt q = cpt_at(g, c);
+        double v[V];
+        cpt_load<DIM>(q, n, [&](int j) { return wk.r[0][j]; }, v);
+        double rv;
+        const double wn = cpt_apply<DIM>(q, v, rv, twod, s);
+        if (q.m & CP_VALID) {
+            wk.w[0][q.c] = wn;
+            ga_p = __builtin_fma(rv, rv, ga_p);
+            de_p = __builtin_fma(wn, rv, de_p);
+        }
+    }
+    double gamma, delta;
+    if (!team_reduce2(tm, ga_p, de_p, wk.red, gamma, delta, lds)) return -1;
+    const double thresh = from_zero ? (abs_thresh2 > 0.0 ? abs_thresh2 : tol * tol * bb) : tol * tol * bb;
+    double alpha = gamma / delta, beta = 0.0;
+    bool first = true;
+    int it = 0;
+    while (it < maxit && gamma > thresh) {
+        const double *ro = wk.r[cur], *wo = wk.w[cur], *so = wk.s[cur];
+        double *rn = wk.r[cur ^ 1], *wn = wk.w[cur ^ 1], *sn = wk.s[cur ^ 1];
+        ga_p = 0.0;
+        de_p = 0.0;
+        for (long long c = cr.begin + wv; c < cr.end; c += nw) {
+            const CPt q = cpt_at(g, c);
+            double rv[V], wvv[V], sv[V];
+            cpt_load<DIM>(q, n, [&](int j) { return ro[j]; }, rv);
+            cpt_load<DIM>(q, n, [&](int j) { return wo[j]; }, wvv);
+            if (first) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) sv[k] = 0.0;
+            } else {
+                cpt_load<DIM>(q, n, [&](int j) { return so[j]; }, sv);
+            }
+            const double pold = first ? 0.0 : wk.p[q.c];
+            const double xold = x[q.c];
+            double rnv[V];   // r' at the point and its neighbours
+#pragma unroll
+            for (int k = 0; k < V; ++k) rnv[k] = __builtin_fma(-alpha, __builtin_fma(beta, sv[k], wvv[k]), rv[k]);
+            double rc;
+            const double wnew = cpt_apply<DIM>(q, rnv, rc, twod, s);
+            if (q.m & CP_VALID) {
+                const double pc = __builtin_fma(beta, pold, rv[0]);
+                sn[q.c] = __builtin_fma(beta, sv[0], wvv[0]);
+                wk.p[q.c] = pc;
+                x[q.c] = __builtin_fma(alpha, pc, xold);
+                rn[q.c] = rc;
+                wn[q.c] = wnew;
+                ga_p = __builtin_fma(rc, rc, ga_p);
+                de_p = __builtin_fma(wnew, rc, de_p);
+            }
+        }
+        double gnew, dnew;
+        if (!team_reduce2(tm, ga_p, de_p, wk.red, gnew, dnew, lds)) return -1;
+        ++it;
+        beta = gnew / gamma;
+        alpha = gnew / (dnew - beta * gnew / alpha);
+        gamma = gnew;
+        cur ^= 1;
+        first = false;
     }
     return it;
 }

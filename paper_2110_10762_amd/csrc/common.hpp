@@ -293,4 +293,39 @@ __device__ __forceinline__ bool team_reduce(Team &tm, double part, double *base,
     return true;
 }
 
+// Two sums at once, one barrier.  `base` holds 4 * size slots: set 0 is
+// [0, size) and [2 size, 3 size), set 1 is [size, 2 size) and [3 size,
+// 4 size), so the sets alternate with those of team_reduce without overlap.
+__device__ __forceinline__ bool team_reduce2(Team &tm, double a, double b, double *base, double &oa, double &ob,
+                                             double *lds) {
+    double *bufa = base + (long long)tm.rpar * tm.size;
+    double *bufb = bufa + 2LL * tm.size;
+    tm.rpar ^= 1;
+    a = block_reduce<false>(a, lds);
+    b = block_reduce<false>(b, lds);
+    if (threadIdx.x == 0) {
+        bufa[tm.rank] = a;
+        bufb[tm.rank] = b;
+    }
+    if (!team_sync(tm)) return false;
+    if (threadIdx.x < WAVE) {
+        double sa = 0.0, sb = 0.0;
+        for (int j = threadIdx.x; j < tm.size; j += WAVE) {
+            sa += bufa[j];
+            sb += bufb[j];
+        }
+        sa = wave_sum(sa);
+        sb = wave_sum(sb);
+        if (threadIdx.x == 0) {
+            lds[0] = sa;
+            lds[1] = sb;
+        }
+    }
+    __syncthreads();
+    oa = uniform(lds[0]);
+    ob = uniform(lds[1]);
+    __syncthreads();
+    return true;
+}
+
 }  // namespace pr

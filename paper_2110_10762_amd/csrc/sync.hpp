@@ -40,6 +40,7 @@ struct SweepArgs {
     double cg_tol;
     int cg_maxit;
     CGWork wk;
+    CGWork1 wk1;        // whole-GPU sweeps: one-synchronisation CG
     unsigned *ctr;
     Control *ctl;
 };
@@ -115,9 +116,20 @@ struct SweepBufs {
 };
 
 template <int DIM>
+__device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
+                                       const double *b, double *x, const CGWork &wk, double abs_thresh2) {
+    return cg_team_dim<DIM, DIM == 3 ? 1 : 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+}
+template <int DIM>
+__device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
+                                       const double *b, double *x, const CGWork1 &wk, double abs_thresh2) {
+    return cg_team_sync1<DIM>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+}
+
+template <int DIM, typename WK>
 __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol, int maxit, long long npts,
                                   int i0, int i1, int kguard, bool init, bool incr, const SweepBufs &B,
-                                  const CGWork &wk, double &dmax, unsigned long long &its, double *lds) {
+                                  const WK &wk, double &dmax, unsigned long long &its, double *lds) {
     const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
     const int w = wave_id();
     const int nw = nwaves();
@@ -131,9 +143,8 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
         const double *vi = B.v + (long long)i * npts;
         if (!skip) {
             // one call site: the kernel holds a single copy of the solver
-            const int it = cg_team_dim<DIM, DIM == 3 ? 1 : 2>(tm, g, s, tol, maxit,
-                                                              incr ? dprev : B.lam + (long long)(i - 1) * npts,
-                                                              B.wn, wk, incr ? tol * tol * nrm_prev : -1.0);
+            const int it = team_cg<DIM>(tm, g, s, tol, maxit, incr ? dprev : B.lam + (long long)(i - 1) * npts,
+                                        B.wn, wk, incr ? tol * tol * nrm_prev : -1.0);
             if (it < 0) return false;
             its += (unsigned long long)it;
         }
@@ -184,7 +195,7 @@ __global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
     unsigned long long its = 0;
     const SweepBufs B{a.lam, a.v, a.w, a.wn, a.d0, a.d1};
     if (!team_coarse_sweep<DIM>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
-                           a.incr != 0, B, a.wk, dmax, its, lds))
+                           a.incr != 0, B, a.wk1, dmax, its, lds))
         return;
     dmax = block_reduce<true>(dmax, lds);
     if (threadIdx.x == 0) {
