@@ -166,13 +166,11 @@ def main():
     value = lups / wall / 1e9
 
     # ---- roofline objects (algorithmic bytes per launch / live event durations)
-    # Algorithmic bytes per point: F pass 16 (read + write the state).
-    # Whole-GPU sweep CG (one synchronisation per iteration): iteration 80
-    # (reads r, w, s_old, p_old, x; writes s, p, x, r', w'), set-up 40 (read
-    # b, write x, r0; read r0, write w0).  Team CG of the async kernel:
-    # iteration 64 (phase A reads r, p_old, writes p; phase B reads p, x, r,
-    # writes x, r), set-up 24 (read b, write x, r).  Correction 48 (read v,
-    # w_new, w_old, lambda_old, write lambda, w).
+    # Algorithmic bytes per point: F pass 16 (read + write the state).  2D
+    # CG (sync sweep and async teams; products recomputed from r and p):
+    # iteration 48 (reads r, p_old, x; writes p, x, r'), set-up 24 (read b,
+    # write x, r0).  Correction 48 (read v, w_new, w_old, lambda_old, write
+    # lambda, w).
     D = info.tb_depth
     passes = -(-m // D)
     fine_kernel = fine_kernel_name(info)
@@ -187,7 +185,7 @@ def main():
                       "launches": f_launches, "avg_launch_ms": f_ms / f_launches,
                       "glups": sum(x["fine_lups"] for x in s) / (f_ms * 1e-3) / 1e9}
         c_ms = sum(x["coarse_ms"] for x in s)
-        c_bytes = sum(x["cg_iters"] * 80.0 * npts + x["g_solves"] * 40.0 * npts
+        c_bytes = sum(x["cg_iters"] * 48.0 * npts + x["g_solves"] * 24.0 * npts
                       + (x["g_solves"] + x["g_skipped"]) * 48.0 * npts for x in s)
         c_launches = sum(x["iters"] + 1 for x in s)
         rl["sweep"] = {"kernel": "k_sweep_cg", "bound": "hbm", "achieved": c_bytes / (c_ms * 1e-3) / 1e9,
@@ -202,7 +200,7 @@ def main():
             upd = x["kernel_updates"]
             solves = x["g_solves"] - N          # minus the initial coarse sweep
             # per update: F passes, predecessor copy 16, correction + next slot 48
-            a_bytes += (upd * (a_passes * 16.0 + 16.0 + 48.0) + x["kernel_cg_iters"] * 64.0
+            a_bytes += (upd * (a_passes * 16.0 + 16.0 + 48.0) + x["kernel_cg_iters"] * 48.0
                         + solves * 24.0) * npts
         rl["async"] = {"kernel": f"k_async<2,2,128,{ASYNC_DEPTH}>", "bound": "hbm",
                        "achieved": a_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -79,7 +79,7 @@ struct AsyncWork {
     unsigned *tctr = nullptr;
     long long *tbc = nullptr;
     double *tred = nullptr;
-    double *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr, *cgb = nullptr;
+    double *cgr = nullptr, *cgr1 = nullptr, *cgp0 = nullptr, *cgp1 = nullptr, *cgb = nullptr;
     unsigned long long *counters = nullptr;
     unsigned long long *pub_t = nullptr;   // [(N+1) R] publication time of each slot's version
     int *pipe = nullptr;                   // PIPELINED: [N+2] publications per version, then K*
@@ -118,8 +118,8 @@ struct AsyncArgs {
     const int *team_of, *rank_of, *tsize;   // per workgroup / per team
     unsigned *tctr;          // [nteams * 16]
     long long *tbc;          // [nteams * 16] leader broadcasts
-    double *tred;            // [nteams * 2 * maxtsz]
-    double *cgr, *cgp0, *cgp1;   // [nteams * cgs]
+    double *tred;            // [nteams * 6 * maxtsz]
+    double *cgr, *cgr1, *cgp0, *cgp1;   // [nteams * cgs]
     long long cgs;               // per-team stride of the CG vectors
     Control *ctl;
     unsigned long long *counters;   // cg iterations, coarse solves, skipped solves, copy retries, idle rounds
@@ -321,7 +321,7 @@ __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const do
 // ---- coarse solve of one state by a team; returns iterations or -1
 template <int DIM, int RR>
 __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double *x, const CGWork &wk,
-                           double abs_thresh2 = -1.0) {
+                           const CGWork2 &wk2, double abs_thresh2 = -1.0) {
     if constexpr (DIM == 1) {
         if (wave_id() == 0) {
             double v[RR], inv[RR];
@@ -341,9 +341,16 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
         }
         return team_sync(tm) ? 0 : -1;
     } else {
-        // one chunk per loop trip: the persistent kernel also holds the fine
-        // propagator and the slice state, so registers decide its occupancy
-        const int it = cg_team_dim<DIM, 1>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
+        // 2D: one synchronisation per iteration and 48 B per point, two
+        // chunks in flight per wave (a team sweeps a whole state with a
+        // fraction of the chip, so each wave walks many chunks and the
+        // latency of its loads, not the bandwidth, sets the pace).  3D: one
+        // chunk per loop trip (the kernel's registers set its occupancy).
+        int it;
+        if constexpr (DIM == 2)
+            it = cg_team_2d_r<2>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk2, abs_thresh2);
+        else
+            it = cg_team_dim<DIM, 1>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
         if (it < 0) return -1;
         return team_sync(tm) ? it : -1;
     }
@@ -355,7 +362,9 @@ enum { ACT_IDLE = 0, ACT_UPDATE = 1, ACT_DONE = 2 };
 // stay in scalar registers, where a by-value struct passed on by reference
 // would be copied to scratch.
 template <int DIM, int XP, int RR, int D, bool IMPL = false>
-__global__ __launch_bounds__(BLOCK, DIM == 2 ? 3 : (DIM == 3 ? 2 : 1)) void k_async(const AsyncArgs *__restrict__ ap) {
+// Two workgroups per CU in 2D and 3D: 256 registers per lane, room for the
+// two chunks in flight of the 2D coarse solver without spills.
+__global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncArgs *__restrict__ ap) {
     const AsyncArgs &a = *ap;
     const int team = a.team_of[blockIdx.x];
     if (team < 0) return;
@@ -363,9 +372,10 @@ __global__ __launch_bounds__(BLOCK, DIM == 2 ? 3 : (DIM == 3 ? 2 : 1)) void k_as
     Team tm{a.tctr + (long long)team * team_counter_words(a.maxtsz), a.ctl, a.tsize[team], rank, 0u};
     if (!team_setup(tm)) return;
     long long *bc = a.tbc + team * 16;
+    double *const tred = a.tred + (long long)team * 6 * a.maxtsz;
     CGWork wk{a.cgr + (long long)team * a.cgs, a.cgp0 + (long long)team * a.cgs,
-              a.cgp1 + (long long)team * a.cgs,
-              a.tred + (long long)team * 2 * a.maxtsz};
+              a.cgp1 + (long long)team * a.cgs, tred};
+    const CGWork2 wk2{{wk.r, a.cgr1 + (long long)team * a.cgs}, {wk.p0, wk.p1}, tred};
     __shared__ double lds[MAX_WAVES];
     const bool leader = (rank == 0 && threadIdx.x == 0);
     const long long np = a.npts;
@@ -564,7 +574,7 @@ __global__ __launch_bounds__(BLOCK, DIM == 2 ? 3 : (DIM == 3 ? 2 : 1)) void k_as
                     if (!team_reduce<false>(tm, nrm_part, wk.red, nrm, lds)) goto out;
                     thr = a.cg_tol * a.cg_tol * nrm;
                 }
-                const int it = team_coarse<DIM, RR>(tm, a, a.incr ? dbuf : x_new, a.incr ? ybuf : w_new, wk, thr);
+                const int it = team_coarse<DIM, RR>(tm, a, a.incr ? dbuf : x_new, a.incr ? ybuf : w_new, wk, wk2, thr);
                 if (it < 0) goto out;
                 cg_its += (unsigned long long)it;
                 ++g_solves;

@@ -428,19 +428,19 @@ __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int ma
 // bit); r, w and s are double-buffered because neighbours read the old ones
 // while the new ones are written.  80 B of HBM traffic per point and
 // iteration (reads r, w, s_old, p_old, x; writes s, p, x, r', w').  Same
-// start and stop rules as cg_team_dim; the iterates agree with it up to
-// rounding.  For whole-GPU teams, whose barriers span the XCDs.
+// start and stop rules and the same U (chunks per wave and loop trip) as
+// cg_team_dim; the iterates agree with it up to rounding.  For whole-GPU
+// teams, whose barriers span the XCDs.
 struct CGWork1 {
     double *r[2], *w[2], *s[2], *p;   // [npts] each
     double *red;                      // [4 * team size] reduction slots
 };
 
-template <int DIM>
+template <int DIM, int U>
 __device__ int cg_team_sync1(Team &tm, const Geom &g, double s, double tol, int maxit,
                              const double *__restrict__ b, double *__restrict__ x, const CGWork1 &wk,
                              double abs_thresh2) {
     constexpr int V = 2 * DIM;
-    __shared__ double lds[MAX_WAVES];
     const double twod = 2.0 * DIM;
     const int n = g.n;
     const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
@@ -464,7 +464,7 @@ __device__ int cg_team_sync1(Team &tm, const Geom &g, double s, double tol, int 
         }
     }
     double bb, unused;
-    if (!team_reduce2(tm, bb_p, 0.0, wk.red, bb, unused, lds)) return -1;
+    if (!team_reduce2(tm, bb_p, 0.0, wk.red, bb, unused)) return -1;
     // w0 = A r0, gamma = (r0, r0), delta = (w0, r0)
     double ga_p = 0.0, de_p = 0.0;
     for (long long c = cr.begin + wv; c < cr.end; c += nw) {
@@ -480,7 +480,7 @@ __device__ int cg_team_sync1(Team &tm, const Geom &g, double s, double tol, int 
         }
     }
     double gamma, delta;
-    if (!team_reduce2(tm, ga_p, de_p, wk.red, gamma, delta, lds)) return -1;
+    if (!team_reduce2(tm, ga_p, de_p, wk.red, gamma, delta)) return -1;
     const double thresh = from_zero ? (abs_thresh2 > 0.0 ? abs_thresh2 : tol * tol * bb) : tol * tol * bb;
     double alpha = gamma / delta, beta = 0.0;
     bool first = true;
@@ -490,43 +490,294 @@ __device__ int cg_team_sync1(Team &tm, const Geom &g, double s, double tol, int 
         double *rn = wk.r[cur ^ 1], *wn = wk.w[cur ^ 1], *sn = wk.s[cur ^ 1];
         ga_p = 0.0;
         de_p = 0.0;
-        for (long long c = cr.begin + wv; c < cr.end; c += nw) {
-            const CPt q = cpt_at(g, c);
-            double rv[V], wvv[V], sv[V];
-            cpt_load<DIM>(q, n, [&](int j) { return ro[j]; }, rv);
-            cpt_load<DIM>(q, n, [&](int j) { return wo[j]; }, wvv);
-            if (first) {
+        for (long long c0 = cr.begin + wv; c0 < cr.end; c0 += U * nw) {
+            CPt q[U];
+            bool act[U];
+            double rv[U][V], wvv[U][V], sv[U][V], pold[U], xold[U];
 #pragma unroll
-                for (int k = 0; k < V; ++k) sv[k] = 0.0;
-            } else {
-                cpt_load<DIM>(q, n, [&](int j) { return so[j]; }, sv);
+            for (int u = 0; u < U; ++u) {
+                const long long c = c0 + u * nw;
+                act[u] = c < cr.end;
+                q[u] = cpt_at(g, act[u] ? c : c0);
+                cpt_load<DIM>(q[u], n, [&](int j) { return ro[j]; }, rv[u]);
+                cpt_load<DIM>(q[u], n, [&](int j) { return wo[j]; }, wvv[u]);
+                if (first) {
+#pragma unroll
+                    for (int k = 0; k < V; ++k) sv[u][k] = 0.0;
+                    pold[u] = 0.0;
+                } else {
+                    cpt_load<DIM>(q[u], n, [&](int j) { return so[j]; }, sv[u]);
+                    pold[u] = wk.p[q[u].c];
+                }
+                xold[u] = x[q[u].c];
             }
-            const double pold = first ? 0.0 : wk.p[q.c];
-            const double xold = x[q.c];
-            double rnv[V];   // r' at the point and its neighbours
 #pragma unroll
-            for (int k = 0; k < V; ++k) rnv[k] = __builtin_fma(-alpha, __builtin_fma(beta, sv[k], wvv[k]), rv[k]);
-            double rc;
-            const double wnew = cpt_apply<DIM>(q, rnv, rc, twod, s);
-            if (q.m & CP_VALID) {
-                const double pc = __builtin_fma(beta, pold, rv[0]);
-                sn[q.c] = __builtin_fma(beta, sv[0], wvv[0]);
-                wk.p[q.c] = pc;
-                x[q.c] = __builtin_fma(alpha, pc, xold);
-                rn[q.c] = rc;
-                wn[q.c] = wnew;
-                ga_p = __builtin_fma(rc, rc, ga_p);
-                de_p = __builtin_fma(wnew, rc, de_p);
+            for (int u = 0; u < U; ++u) {
+                double rnv[V];   // r' at the point and its neighbours
+#pragma unroll
+                for (int k = 0; k < V; ++k)
+                    rnv[k] = __builtin_fma(-alpha, __builtin_fma(beta, sv[u][k], wvv[u][k]), rv[u][k]);
+                double rc;
+                const double wnew = cpt_apply<DIM>(q[u], rnv, rc, twod, s);
+                if (act[u] && (q[u].m & CP_VALID)) {
+                    const int i = q[u].c;
+                    const double pc = __builtin_fma(beta, pold[u], rv[u][0]);
+                    sn[i] = __builtin_fma(beta, sv[u][0], wvv[u][0]);
+                    wk.p[i] = pc;
+                    x[i] = __builtin_fma(alpha, pc, xold[u]);
+                    rn[i] = rc;
+                    wn[i] = wnew;
+                    ga_p = __builtin_fma(rc, rc, ga_p);
+                    de_p = __builtin_fma(wnew, rc, de_p);
+                }
             }
         }
         double gnew, dnew;
-        if (!team_reduce2(tm, ga_p, de_p, wk.red, gnew, dnew, lds)) return -1;
+        if (!team_reduce2(tm, ga_p, de_p, wk.red, gnew, dnew)) return -1;
         ++it;
         beta = gnew / gamma;
         alpha = gnew / (dnew - beta * gnew / alpha);
         gamma = gnew;
         cur ^= 1;
         first = false;
+    }
+    return it;
+}
+
+// ------------------------------------------------------------------ 2D CG, products recomputed
+// The one-synchronisation CG above with neither w = A r nor s = A p stored:
+// a wave recomputes A p at the point and its four neighbours from p (hence
+// p at distance 2), updates r there, and forms w' = A r' at the point.
+// Stored state: x, r, p (r and p double-buffered), 48 B of HBM traffic per
+// point and iteration; the extra reads of the distance-2 rows hit the
+// caches.  Iteration i:
+//   p_i = r_i + beta_i p_{i-1},  x_{i+1} = x_i + alpha_i p_i,
+//   r_{i+1} = r_i - alpha_i A p_i,  gamma = (r_{i+1}, r_{i+1}),
+//   delta = (A r_{i+1}, r_{i+1}),  beta_{i+1} = gamma_{i+1} / gamma_i,
+//   alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1} / alpha_i).
+// Every value at a point (p, A p, r') is formed by the same operations in
+// the same order wherever it is needed, so all copies agree bit for bit.
+struct CGWork2 {
+    double *r[2], *p[2];   // [npts] each
+    double *red;           // [6 * team size] reduction slots
+};
+
+// A chunk point of the distance-2 star: its index, the addresses of the
+// loads (missing points read the point itself and are masked) and masks.
+struct D2Pt {
+    int c;                    // the point (the row start for lanes past the row end)
+    int u, d, uu, dd;         // rows y-1, y+1, y-2, y+2 at x
+    int e1, e2, ue, de;       // lane 0: x-1, x-2, (x-1, y-1), (x-1, y+1); lane 63: the same at x+1, x+2
+    unsigned m;
+};
+constexpr unsigned D2_V = 1, D2_U = 2, D2_D = 4, D2_UU = 8, D2_DD = 16, D2_E1 = 32, D2_E2 = 64, D2_XL = 128,
+                   D2_XR = 256;
+
+__device__ __forceinline__ D2Pt d2_at(const Geom &g, long long chunk) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const Point p = chunk_point(g, chunk);
+    const int n = g.n;
+    D2Pt q;
+    q.c = (int)(p.valid ? p.idx : p.idx - p.x);
+    unsigned m = 0;
+    const bool up = p.y > 0, dn = p.y + 1 < n, uu = p.y > 1, dd = p.y + 2 < n;
+    if (p.valid) {
+        m |= D2_V;
+        if (up) m |= D2_U;
+        if (dn) m |= D2_D;
+        if (uu) m |= D2_UU;
+        if (dd) m |= D2_DD;
+        if (p.x > 0) m |= D2_XL;
+        if (p.x + 1 < n) m |= D2_XR;
+    }
+    // edge lanes: the neighbours across the chunk border (lane 0 is always
+    // valid; lane 63's right neighbours exist only inside the row)
+    int e1 = q.c, e2 = q.c;
+    if (lane == 0 && p.x > 0) {
+        m |= D2_E1 | D2_E2;   // x >= 64
+        e1 = q.c - 1;
+        e2 = q.c - 2;
+    } else if (lane == WAVE - 1 && p.x + 1 < n) {
+        m |= D2_E1;
+        e1 = q.c + 1;
+        if (p.x + 2 < n) {
+            m |= D2_E2;
+            e2 = q.c + 2;
+        }
+    }
+    q.u = (m & D2_U) ? q.c - n : q.c;
+    q.d = (m & D2_D) ? q.c + n : q.c;
+    q.uu = (m & D2_UU) ? q.c - 2 * n : q.c;
+    q.dd = (m & D2_DD) ? q.c + 2 * n : q.c;
+    q.e1 = e1;
+    q.e2 = e2;
+    q.ue = ((m & D2_E1) && up) ? e1 - n : q.c;
+    q.de = ((m & D2_E1) && dn) ? e1 + n : q.c;
+    q.m = m;
+    return q;
+}
+
+// The 13 values of a state on the distance-2 star of a point (zero outside
+// the domain): row y at x-2..x+2, rows y-1 and y+1 at x-1..x+1, rows y-2 and
+// y+2 at x.
+struct Star13 {
+    double c, l1, l2, r1, r2;
+    double u, ul, ur;
+    double d, dl, dr;
+    double uu, dd;
+};
+
+struct Raw9 {
+    double c, u, d, uu, dd, e1, e2, ue, de;
+};
+
+__device__ __forceinline__ void d2_load(const D2Pt &q, const double *__restrict__ v, Raw9 &w) {
+    w.c = v[q.c];
+    w.u = v[q.u];
+    w.d = v[q.d];
+    w.uu = v[q.uu];
+    w.dd = v[q.dd];
+    w.e1 = v[q.e1];
+    w.e2 = v[q.e2];
+    w.ue = v[q.ue];
+    w.de = v[q.de];
+}
+
+__device__ __forceinline__ Star13 d2_star(const D2Pt &q, const Raw9 &w) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const bool l0 = lane == 0, l63 = lane == WAVE - 1;
+    const unsigned m = q.m;
+    const bool ok = m & D2_V;
+    Star13 t;
+    t.c = ok ? w.c : 0.0;
+    t.u = (m & D2_U) ? w.u : 0.0;      // D2_U etc. imply D2_V
+    t.d = (m & D2_D) ? w.d : 0.0;
+    t.uu = (m & D2_UU) ? w.uu : 0.0;
+    t.dd = (m & D2_DD) ? w.dd : 0.0;
+    const double e1 = (m & D2_E1) ? w.e1 : 0.0;
+    const double e2 = (m & D2_E2) ? w.e2 : 0.0;
+    const double ue = ((m & D2_E1) && (m & D2_U)) ? w.ue : 0.0;
+    const double de = ((m & D2_E1) && (m & D2_D)) ? w.de : 0.0;
+    const double cl = from_lower_lane(t.c), cr = from_upper_lane(t.c);
+    t.l1 = l0 ? e1 : cl;
+    t.r1 = l63 ? e1 : cr;
+    const double ll = from_lower_lane(t.l1), rr = from_upper_lane(t.r1);
+    t.l2 = l0 ? e2 : ll;
+    t.r2 = l63 ? e2 : rr;
+    const double ul = from_lower_lane(t.u), ur = from_upper_lane(t.u);
+    t.ul = l0 ? ue : ul;
+    t.ur = l63 ? ue : ur;
+    const double dl = from_lower_lane(t.d), dr = from_upper_lane(t.d);
+    t.dl = l0 ? de : dl;
+    t.dr = l63 ? de : dr;
+    return t;
+}
+
+// One sweep of the 2D CG: p = r + beta p_old on the star (p = r when
+// `first`), A p at the point and its neighbours, r' = r - alpha A p there
+// (zero outside the domain), w' = A r' at the point; stores x + alpha p, r'
+// and (unless `setup`) p; accumulates (r', r'), (w', r') and (r, r).
+// At set-up r is the right-hand side b, first is set and x is taken as 0.
+template <int U>
+__device__ __forceinline__ void cg2_sweep(const Geom &g, const ChunkRange &cr, double s, double alpha, double beta,
+                                          bool first, bool setup, const double *__restrict__ r,
+                                          const double *__restrict__ pold, double *__restrict__ x,
+                                          double *__restrict__ rnew, double *__restrict__ pnew, double &ga,
+                                          double &de, double &rr) {
+    const int wv = wave_id();
+    const long long nw = nwaves();
+    for (long long c0 = cr.begin + wv; c0 < cr.end; c0 += U * nw) {
+        D2Pt q[U];
+        bool act[U];
+        Raw9 wr[U], wp[U];
+        double xo[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long c = c0 + u * nw;
+            act[u] = c < cr.end;
+            q[u] = d2_at(g, act[u] ? c : c0);
+            d2_load(q[u], r, wr[u]);
+            if (!first) d2_load(q[u], pold, wp[u]);
+            xo[u] = setup ? 0.0 : x[q[u].c];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const Star13 R = d2_star(q[u], wr[u]);
+            Star13 P = R;
+            if (!first) {
+                const Star13 Po = d2_star(q[u], wp[u]);
+                P.c = __builtin_fma(beta, Po.c, R.c);
+                P.l1 = __builtin_fma(beta, Po.l1, R.l1);
+                P.l2 = __builtin_fma(beta, Po.l2, R.l2);
+                P.r1 = __builtin_fma(beta, Po.r1, R.r1);
+                P.r2 = __builtin_fma(beta, Po.r2, R.r2);
+                P.u = __builtin_fma(beta, Po.u, R.u);
+                P.ul = __builtin_fma(beta, Po.ul, R.ul);
+                P.ur = __builtin_fma(beta, Po.ur, R.ur);
+                P.d = __builtin_fma(beta, Po.d, R.d);
+                P.dl = __builtin_fma(beta, Po.dl, R.dl);
+                P.dr = __builtin_fma(beta, Po.dr, R.dr);
+                P.uu = __builtin_fma(beta, Po.uu, R.uu);
+                P.dd = __builtin_fma(beta, Po.dd, R.dd);
+            }
+            // A p at the point and its neighbours: (up + down) + (left + right)
+            const double ap_c = be_point(P.c, (P.u + P.d) + (P.l1 + P.r1), 4.0, s);
+            const double ap_l = be_point(P.l1, (P.ul + P.dl) + (P.l2 + P.c), 4.0, s);
+            const double ap_r = be_point(P.r1, (P.ur + P.dr) + (P.c + P.r2), 4.0, s);
+            const double ap_u = be_point(P.u, (P.uu + P.c) + (P.ul + P.ur), 4.0, s);
+            const double ap_d = be_point(P.d, (P.c + P.dd) + (P.dl + P.dr), 4.0, s);
+            const unsigned m = q[u].m;
+            const double rc = (m & D2_V) ? __builtin_fma(-alpha, ap_c, R.c) : 0.0;
+            const double rl = (m & D2_XL) ? __builtin_fma(-alpha, ap_l, R.l1) : 0.0;
+            const double rrt = (m & D2_XR) ? __builtin_fma(-alpha, ap_r, R.r1) : 0.0;
+            const double ru = (m & D2_U) ? __builtin_fma(-alpha, ap_u, R.u) : 0.0;
+            const double rd = (m & D2_D) ? __builtin_fma(-alpha, ap_d, R.d) : 0.0;
+            const double wn = be_point(rc, (ru + rd) + (rl + rrt), 4.0, s);
+            if (act[u] && (m & D2_V)) {
+                const int i = q[u].c;
+                x[i] = __builtin_fma(alpha, P.c, xo[u]);
+                rnew[i] = rc;
+                if (!setup) pnew[i] = P.c;
+                ga = __builtin_fma(rc, rc, ga);
+                de = __builtin_fma(wn, rc, de);
+                rr = __builtin_fma(R.c, R.c, rr);
+            }
+        }
+    }
+}
+
+// Solves (I - s h^2 L_h) x = b in 2D; same start and stop rules as
+// cg_team_dim (abs_thresh2 < 0: x0 = b, relative stop; >= 0: x0 = 0,
+// absolute stop).  Returns the iteration count, or -1 if the launch was
+// aborted.  x must not alias b or the work vectors.
+template <int U>
+__device__ int cg_team_2d_r(Team &tm, const Geom &g, double s, double tol, int maxit,
+                            const double *__restrict__ b, double *__restrict__ x, const CGWork2 &wk,
+                            double abs_thresh2) {
+    const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
+    const bool from_zero = abs_thresh2 >= 0.0;
+    // set-up: r0 = b - A x0 with x0 = b (alpha = 1) or x0 = 0 (alpha = 0)
+    double part[3] = {0.0, 0.0, 0.0}, tot[3];
+    cg2_sweep<U>(g, cr, s, from_zero ? 0.0 : 1.0, 0.0, true, true, b, nullptr, x, wk.r[0], nullptr, part[0],
+                 part[1], part[2]);
+    if (!team_reduce_n<3>(tm, part, wk.red, tot)) return -1;
+    double gamma = tot[0], delta = tot[1];
+    const double bb = tot[2];
+    const double thresh = from_zero ? (abs_thresh2 > 0.0 ? abs_thresh2 : tol * tol * bb) : tol * tol * bb;
+    double alpha = gamma / delta, beta = 0.0;
+    int cur = 0;
+    int it = 0;
+    while (it < maxit && gamma > thresh) {
+        double pp[2] = {0.0, 0.0}, tt[2];
+        double unused = 0.0;
+        cg2_sweep<U>(g, cr, s, alpha, beta, it == 0, false, wk.r[cur], wk.p[cur], x, wk.r[cur ^ 1],
+                     wk.p[cur ^ 1], pp[0], pp[1], unused);
+        if (!team_reduce_n<2>(tm, pp, wk.red, tt)) return -1;
+        ++it;
+        beta = tt[0] / gamma;
+        alpha = tt[0] / (tt[1] - beta * tt[0] / alpha);
+        gamma = tt[0];
+        cur ^= 1;
     }
     return it;
 }

@@ -157,14 +157,18 @@ __device__ __forceinline__ unsigned ld_relaxed(const unsigned *p) {
 // Polls (single thread) with relaxed atomic loads until (int)(*ctr - target)
 // >= 0, then issues one agent-scope acquire fence.  Returns false if the
 // launch was aborted or the wait ran out (then the launch is aborted).
+// The abort flag is read every 16th poll only: a poll is a round trip to the
+// memory side, and the barrier latency is a chain of them.
 __device__ __forceinline__ bool wait_counter(const unsigned *ctr, unsigned target, Control *ctl) {
     long long spins = 0;
     while ((int)(ld_relaxed(ctr) - target) < 0) {
-        if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-        if (++spins > SPIN_LIMIT) {
-            __hip_atomic_store(&ctl->error, -7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
+        if ((++spins & 15) == 0) {
+            if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+            if (spins > SPIN_LIMIT) {
+                __hip_atomic_store(&ctl->error, -7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
         }
         __builtin_amdgcn_s_sleep(1);
     }
@@ -207,27 +211,42 @@ struct Team {
 };
 
 // Must be called once by every workgroup of the team before any team_sync.
-__device__ __forceinline__ bool team_setup(Team &tm) {
-    __shared__ int s_gx, s_nx, s_ok;
+// xcd_ranks: renumber the workgroups so that those on one XCD hold
+// consecutive ranks (XCD 0 first, arrival order within an XCD); the chunks a
+// rank owns are then neighbours in memory, so the halo rows a workgroup
+// reads mostly sit in its own XCD's L2.  Any numbering gives the same
+// results: a rank's chunk range and reduction slot do not depend on which
+// workgroup holds it.
+__device__ __forceinline__ bool team_setup(Team &tm, bool xcd_ranks = false) {
+    __shared__ int s_gx, s_nx, s_ok, s_rank;
     tm.xcc = xcc_id();
     if (threadIdx.x == 0) {
         bool ok = true;
-        int gx = 1, nx = 1;
+        int gx = 1, nx = 1, rank = tm.rank;
         if (tm.size > 1) {
-            __hip_atomic_fetch_add(tm.ctr + 32 * (17 + tm.xcc), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned ticket = __hip_atomic_fetch_add(tm.ctr + 32 * (17 + tm.xcc), 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(tm.ctr + 32 * 25, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             ok = wait_counter(tm.ctr + 32 * 25, (unsigned)tm.size, tm.ctl);
             nx = 0;
-            for (int x = 0; x < 8; ++x) nx += ld_relaxed(tm.ctr + 32 * (17 + x)) > 0u;
+            int before = 0;
+            for (int x = 0; x < 8; ++x) {
+                const unsigned cx = ld_relaxed(tm.ctr + 32 * (17 + x));
+                nx += cx > 0u;
+                if (x < tm.xcc) before += (int)cx;
+            }
             gx = (int)ld_relaxed(tm.ctr + 32 * (17 + tm.xcc));
+            if (xcd_ranks) rank = before + (int)ticket;
         }
         s_gx = gx;
         s_nx = nx;
         s_ok = ok;
+        s_rank = rank;
     }
     __syncthreads();
     tm.gx = s_gx;
     tm.nx = s_nx;
+    tm.rank = uniform(s_rank);
     tm.epoch = 0;
     tm.rpar = 0;
     const bool ok = s_ok != 0;
@@ -252,19 +271,27 @@ __device__ __forceinline__ bool team_sync(Team &tm) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // write this XCD's L2 back
                 if (tm.nx > 1) {
                     __hip_atomic_fetch_add(tm.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = wait_counter(tm.ctr, tm.epoch * (unsigned)tm.nx, tm.ctl);
+                    ok = wait_counter(tm.ctr, tm.epoch * (unsigned)tm.nx, tm.ctl);   // ends with the acquire
+                } else {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 __hip_atomic_store(tm.ctr + 32 * (9 + tm.xcc), tm.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                ok = wait_counter(tm.ctr + 32 * (9 + tm.xcc), tm.epoch, tm.ctl);
+                ok = wait_counter(tm.ctr + 32 * (9 + tm.xcc), tm.epoch, tm.ctl);   // ends with the acquire
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        s_ok = ok && !__hip_atomic_load(&tm.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // an abort raised elsewhere while this barrier completed is seen at
+        // the next wait
+        s_ok = ok;
     }
     __syncthreads();
     return s_ok != 0;
 }
+
+// Slots a lane loads at once when it sums the team's partials (one round
+// trip for teams of up to 256 workgroups).  Lanes sum their slots j, j + 64,
+// ... in increasing order, padding with zeros, whatever the batch.
+constexpr int SLOT_BATCH = 4;
 
 // Deterministic team all-reduce: every workgroup writes its partial to its
 // slot; after the barrier every workgroup sums (or maxes) the slots in the
@@ -280,9 +307,15 @@ __device__ __forceinline__ bool team_reduce(Team &tm, double part, double *base,
     if (!team_sync(tm)) return false;
     if (threadIdx.x < WAVE) {
         double acc = 0.0;
-        for (int j = threadIdx.x; j < tm.size; j += WAVE) {
-            const double b = buf[j];
-            acc = MAX ? fmax(acc, b) : acc + b;
+        for (int j0 = 0; j0 < tm.size; j0 += SLOT_BATCH * WAVE) {
+            double b[SLOT_BATCH];
+#pragma unroll
+            for (int t = 0; t < SLOT_BATCH; ++t) {
+                const int j = j0 + t * WAVE + (int)threadIdx.x;
+                b[t] = j < tm.size ? buf[j] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < SLOT_BATCH; ++t) acc = MAX ? fmax(acc, b[t]) : acc + b[t];
         }
         const double v = MAX ? wave_max(acc) : wave_sum(acc);
         if (threadIdx.x == 0) lds[0] = v;
@@ -293,38 +326,73 @@ __device__ __forceinline__ bool team_reduce(Team &tm, double part, double *base,
     return true;
 }
 
-// Two sums at once, one barrier.  `base` holds 4 * size slots: set 0 is
-// [0, size) and [2 size, 3 size), set 1 is [size, 2 size) and [3 size,
-// 4 size), so the sets alternate with those of team_reduce without overlap.
-__device__ __forceinline__ bool team_reduce2(Team &tm, double a, double b, double *base, double &oa, double &ob,
-                                             double *lds) {
-    double *bufa = base + (long long)tm.rpar * tm.size;
-    double *bufb = bufa + 2LL * tm.size;
+// K sums at once, one barrier.  `base` holds 2 K * size slots; value k of
+// slot set q (q = 0, 1 alternating) sits at [(2k + q) size, (2k + q + 1)
+// size), so set q of one call never meets set 1 - q of the next, whichever
+// of team_reduce and team_reduce_n makes it.  Per value, the order of the
+// additions is that of team_reduce.
+template <int K>
+__device__ __forceinline__ bool team_reduce_n(Team &tm, const double (&part)[K], double *base, double (&out)[K]) {
+    __shared__ double sl[MAX_WAVES * K];
+    const int q = tm.rpar;
     tm.rpar ^= 1;
-    a = block_reduce<false>(a, lds);
-    b = block_reduce<false>(b, lds);
+    const int w = threadIdx.x / WAVE;
+    const int nw = nwaves();
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(part[k]);
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) sl[w * K + k] = v[k];
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        bufa[tm.rank] = a;
-        bufb[tm.rank] = b;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double t = sl[k];
+            for (int i = 1; i < nw; ++i) t = t + sl[i * K + k];
+            base[(long long)(2 * k + q) * tm.size + tm.rank] = t;
+        }
     }
     if (!team_sync(tm)) return false;
     if (threadIdx.x < WAVE) {
-        double sa = 0.0, sb = 0.0;
-        for (int j = threadIdx.x; j < tm.size; j += WAVE) {
-            sa += bufa[j];
-            sb += bufb[j];
+        double acc[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] = 0.0;
+        for (int j0 = 0; j0 < tm.size; j0 += SLOT_BATCH * WAVE) {
+            double b[K][SLOT_BATCH];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int t = 0; t < SLOT_BATCH; ++t) {
+                    const int j = j0 + t * WAVE + (int)threadIdx.x;
+                    b[k][t] = j < tm.size ? base[(long long)(2 * k + q) * tm.size + j] : 0.0;
+                }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int t = 0; t < SLOT_BATCH; ++t) acc[k] += b[k][t];
         }
-        sa = wave_sum(sa);
-        sb = wave_sum(sb);
-        if (threadIdx.x == 0) {
-            lds[0] = sa;
-            lds[1] = sb;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double r = wave_sum(acc[k]);
+            if (threadIdx.x == 0) sl[k] = r;
         }
     }
     __syncthreads();
-    oa = uniform(lds[0]);
-    ob = uniform(lds[1]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = uniform(sl[k]);
     __syncthreads();
+    return true;
+}
+
+__device__ __forceinline__ bool team_reduce2(Team &tm, double a, double b, double *base, double &oa, double &ob) {
+    const double part[2] = {a, b};
+    double out[2];
+    if (!team_reduce_n<2>(tm, part, base, out)) return false;
+    oa = out[0];
+    ob = out[1];
     return true;
 }
 

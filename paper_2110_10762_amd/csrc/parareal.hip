@@ -490,6 +490,7 @@ static SweepArgs sweep_args(pr_problem *h, const Prob &P, double *lam) {
     a.cg_maxit = P.cg_maxit;
     a.wk = CGWork{h->cg_r, h->cg_p0, h->cg_p1, h->red};
     a.wk1 = CGWork1{{h->cg_r, h->cg_p0}, {h->cg_p1, h->cg1[0]}, {h->cg1[1], h->cg1[2]}, h->cg1[3], h->red};
+    a.wk2 = CGWork2{{h->cg_r, h->cg_p0}, {h->cg_p1, h->cg1[0]}, h->red};
     a.ctr = h->ctr;
     a.ctl = h->ctl;
     return a;

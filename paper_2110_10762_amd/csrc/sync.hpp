@@ -40,7 +40,8 @@ struct SweepArgs {
     double cg_tol;
     int cg_maxit;
     CGWork wk;
-    CGWork1 wk1;        // whole-GPU sweeps: one-synchronisation CG
+    CGWork1 wk1;        // whole-GPU sweeps: one-synchronisation CG (3D)
+    CGWork2 wk2;        //                   and with recomputed products (2D)
     unsigned *ctr;
     Control *ctl;
 };
@@ -123,7 +124,14 @@ __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWork1 &wk, double abs_thresh2) {
-    return cg_team_sync1<DIM>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+    return cg_team_sync1<DIM, DIM == 3 ? 1 : 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+}
+
+template <int DIM>
+__device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
+                                       const double *b, double *x, const CGWork2 &wk, double abs_thresh2) {
+    static_assert(DIM == 2, "the recomputing CG is two-dimensional");
+    return cg_team_2d_r<1>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
 
 template <int DIM, typename WK>
@@ -189,14 +197,19 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
 template <int DIM>
 __global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
     Team tm{a.ctr, a.ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
-    if (!team_setup(tm)) return;
+    if (!team_setup(tm, true)) return;
     __shared__ double lds[MAX_WAVES];
     double dmax = 0.0;
     unsigned long long its = 0;
     const SweepBufs B{a.lam, a.v, a.w, a.wn, a.d0, a.d1};
-    if (!team_coarse_sweep<DIM>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
-                           a.incr != 0, B, a.wk1, dmax, its, lds))
-        return;
+    bool ok;
+    if constexpr (DIM == 2)
+        ok = team_coarse_sweep<2>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
+                                  a.incr != 0, B, a.wk2, dmax, its, lds);
+    else
+        ok = team_coarse_sweep<3>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
+                                  a.incr != 0, B, a.wk1, dmax, its, lds);
+    if (!ok) return;
     dmax = block_reduce<true>(dmax, lds);
     if (threadIdx.x == 0) {
         if (!a.init) atomic_max_nonneg(a.delta, dmax);
