@@ -341,14 +341,15 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
         }
         return team_sync(tm) ? 0 : -1;
     } else {
-        // 2D: one synchronisation per iteration and 48 B per point, two
-        // chunks in flight per wave (a team sweeps a whole state with a
-        // fraction of the chip, so each wave walks many chunks and the
-        // latency of its loads, not the bandwidth, sets the pace).  3D: one
+        // 2D: one synchronisation per iteration, 48 B per point, and the
+        // marching sweep: a team sweeps a whole state with an eighth of the
+        // chip or less, so each wave owns a long run of rows and streams it
+        // with its loads four rows ahead (1.33x faster than chunks visited
+        // one or two at a time, whose load latency set the pace).  3D: one
         // chunk per loop trip (the kernel's registers set its occupancy).
         int it;
         if constexpr (DIM == 2)
-            it = cg_team_2d_r<2>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk2, abs_thresh2);
+            it = cg_team_2d_r<1, true>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk2, abs_thresh2);
         else
             it = cg_team_dim<DIM, 1>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
         if (it < 0) return -1;

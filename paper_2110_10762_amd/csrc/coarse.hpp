@@ -746,20 +746,181 @@ __device__ __forceinline__ void cg2_sweep(const Geom &g, const ChunkRange &cr, d
     }
 }
 
+// The same sweep for a team whose waves each own a long run of rows: a
+// wave takes a strip of 64 columns and a segment of rows and marches down
+// it, loading each input row of r and p_old once (4 rows ahead, so their
+// loads are in flight together) and keeping the last rows of p, A p and r'
+// in registers.  Every value is formed exactly as in cg2_sweep (the same
+// operations in the same order); only the order in which the partial sums
+// are accumulated differs.
+struct SWRow {          // raw loads of one input row: centre and the two edge points
+    double rc, r1, r2, pc, p1, p2, xo;
+};
+
+__device__ __forceinline__ void sw_issue(const double *__restrict__ r, const double *__restrict__ pold,
+                                         const double *__restrict__ x, int n, int k, int xcol, bool lv, int e1off,
+                                         int e2off, bool e1ok, bool e2ok, bool first, bool setup, bool xrow,
+                                         SWRow &w) {
+    const bool rowok = k >= 0 && k < n;
+    const int base = rowok ? k * n + xcol : 0;
+    const int ic = (rowok && lv) ? base : 0;
+    const int i1 = (rowok && e1ok) ? base + e1off : 0;
+    const int i2 = (rowok && e2ok) ? base + e2off : 0;
+    w.rc = r[ic];
+    w.r1 = r[i1];
+    w.r2 = r[i2];
+    if (!first) {
+        w.pc = pold[ic];
+        w.p1 = pold[i1];
+        w.p2 = pold[i2];
+    }
+    // x of the output row (two rows behind the input row)
+    w.xo = (!setup && xrow && lv) ? x[(k - 2) * n + xcol] : 0.0;
+}
+
+template <int PF, int MINSEG>
+__device__ __forceinline__ void cg2_sweep_sw(const Geom &g, int rank, int size, double s, double alpha,
+                                             double beta, bool first, bool setup, const double *__restrict__ r,
+                                             const double *__restrict__ pold, double *__restrict__ x,
+                                             double *__restrict__ rnew, double *__restrict__ pnew, double &ga,
+                                             double &de, double &rr) {
+    const int n = g.n;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const bool l0 = lane == 0, l63 = lane == WAVE - 1;
+    const int waves = size * nwaves();
+    const int wid = rank * nwaves() + wave_id();
+    // segments of rows: about one (strip, segment) unit per wave, at least MINSEG rows
+    const int per = (int)(((long long)n * g.cpr + waves - 1) / waves);
+    const int seg = max(MINSEG, per);
+    const int nseg = (n + seg - 1) / seg;
+    const int units = g.cpr * nseg;
+    for (int u = wid; u < units; u += waves) {
+        const int sx = u % g.cpr;
+        const int ya = (u / g.cpr) * seg;
+        const int yb = min(n, ya + seg);
+        const int xcol = sx * WAVE + lane;
+        const bool lv = xcol < n;
+        const bool xl = lv && xcol > 0, xr = xcol + 1 < n;
+        // edge points across the strip border (lane 0 is always inside the row)
+        const bool e1ok = (l0 && xcol > 0) || (l63 && xcol + 1 < n);
+        const bool e2ok = (l0 && xcol > 0) || (l63 && xcol + 2 < n);
+        const int e1off = l0 ? -1 : 1, e2off = l0 ? -2 : 2;
+        const int nrows = yb - ya + 4;   // input rows ya-2 .. yb+1
+        // window: p at rows k-2 (c, l1, r1) and k-1 (c, l1, r1, l2, r2); r at
+        // row k-1 (c, l1, r1) and the centre of row k-2; r' at rows k-3
+        // (centre) and k-2 (c, l, r)
+        double pm2c = 0, pm2l = 0, pm2r = 0, pm1c = 0, pm1l = 0, pm1r = 0, pm1l2 = 0, pm1r2 = 0;
+        double rm1c = 0, rm1l = 0, rm1r = 0, rm2c = 0;
+        double qm3c = 0, qm2c = 0, qm2l = 0, qm2r = 0;
+        SWRow ring[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = ya - 2 + q;
+            if (q < nrows)
+                sw_issue(r, pold, x, n, k, xcol, lv, e1off, e2off, e1ok, e2ok, first, setup,
+                         k - 2 >= ya && k - 2 < yb, ring[q]);
+        }
+        for (int tb = 0; tb < nrows; tb += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int t = tb + q;
+                if (t >= nrows) break;
+                const int k = ya - 2 + t;
+                const bool rowok = k >= 0 && k < n;
+                // row k: r and p (masked), then refill the slot
+                const SWRow w = ring[q];
+                if (t + PF < nrows) {
+                    const int kk = k + PF;
+                    sw_issue(r, pold, x, n, kk, xcol, lv, e1off, e2off, e1ok, e2ok, first, setup,
+                             kk - 2 >= ya && kk - 2 < yb, ring[q]);
+                }
+                const double Rc = (rowok && lv) ? w.rc : 0.0;
+                const double R1 = (rowok && e1ok) ? w.r1 : 0.0;
+                const double R2 = (rowok && e2ok) ? w.r2 : 0.0;
+                double Pc = Rc, P1 = R1, P2 = R2;
+                if (!first) {
+                    Pc = __builtin_fma(beta, (rowok && lv) ? w.pc : 0.0, Rc);
+                    P1 = __builtin_fma(beta, (rowok && e1ok) ? w.p1 : 0.0, R1);
+                    P2 = __builtin_fma(beta, (rowok && e2ok) ? w.p2 : 0.0, R2);
+                }
+                // lane shifts first, on every lane: a shift evaluated only where
+                // the edge test fails would read inactive lanes as zero
+                const double sRl = from_lower_lane(Rc), sRr = from_upper_lane(Rc);
+                const double sPl = from_lower_lane(Pc), sPr = from_upper_lane(Pc);
+                const double Rl = l0 ? R1 : sRl;
+                const double Rr = l63 ? R1 : sRr;
+                const double Pl = l0 ? P1 : sPl;
+                const double Pr = l63 ? P1 : sPr;
+                const double sPl2 = from_lower_lane(Pl), sPr2 = from_upper_lane(Pr);
+                const double Pl2 = l0 ? P2 : sPl2;
+                const double Pr2 = l63 ? P2 : sPr2;
+                // row j = k-1: A p at (x, j), (x-1, j), (x+1, j); r' there
+                const int j = k - 1;
+                const bool jok = j >= 0 && j < n;
+                const double apc = be_point(pm1c, (pm2c + Pc) + (pm1l + pm1r), 4.0, s);
+                const double apl = be_point(pm1l, (pm2l + Pl) + (pm1l2 + pm1c), 4.0, s);
+                const double apr = be_point(pm1r, (pm2r + Pr) + (pm1c + pm1r2), 4.0, s);
+                const double qc = (jok && lv) ? __builtin_fma(-alpha, apc, rm1c) : 0.0;
+                const double ql = (jok && xl) ? __builtin_fma(-alpha, apl, rm1l) : 0.0;
+                const double qr = (jok && xr) ? __builtin_fma(-alpha, apr, rm1r) : 0.0;
+                // row y = k-2: A r' at (x, y), stores, partial sums
+                const int y = k - 2;
+                if (y >= ya && y < yb) {
+                    const double wn = be_point(qm2c, (qm3c + qc) + (qm2l + qm2r), 4.0, s);
+                    if (lv) {
+                        const int i = y * n + xcol;
+                        x[i] = __builtin_fma(alpha, pm2c, w.xo);
+                        rnew[i] = qm2c;
+                        if (!setup) pnew[i] = pm2c;
+                        ga = __builtin_fma(qm2c, qm2c, ga);
+                        de = __builtin_fma(wn, qm2c, de);
+                        rr = __builtin_fma(rm2c, rm2c, rr);
+                    }
+                }
+                // shift the window
+                qm3c = qm2c;
+                qm2c = qc;
+                qm2l = ql;
+                qm2r = qr;
+                rm2c = rm1c;
+                rm1c = Rc;
+                rm1l = Rl;
+                rm1r = Rr;
+                pm2c = pm1c;
+                pm2l = pm1l;
+                pm2r = pm1r;
+                pm1c = Pc;
+                pm1l = Pl;
+                pm1r = Pr;
+                pm1l2 = Pl2;
+                pm1r2 = Pr2;
+            }
+        }
+    }
+}
+
 // Solves (I - s h^2 L_h) x = b in 2D; same start and stop rules as
 // cg_team_dim (abs_thresh2 < 0: x0 = b, relative stop; >= 0: x0 = 0,
 // absolute stop).  Returns the iteration count, or -1 if the launch was
 // aborted.  x must not alias b or the work vectors.
-template <int U>
+// SW: the marching sweep (teams that own a whole state with few waves).
+template <int U, bool SW = false, int SWSEG = 16, int SWPF = 4>
 __device__ int cg_team_2d_r(Team &tm, const Geom &g, double s, double tol, int maxit,
                             const double *__restrict__ b, double *__restrict__ x, const CGWork2 &wk,
                             double abs_thresh2) {
     const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
     const bool from_zero = abs_thresh2 >= 0.0;
+    auto sweep = [&](double alpha, double beta, bool first, bool setup, const double *r, const double *pold,
+                     double *rnew, double *pnew, double &ga, double &de, double &rr) {
+        if constexpr (SW)
+            cg2_sweep_sw<SWPF, SWSEG>(g, tm.rank, tm.size, s, alpha, beta, first, setup, r, pold, x, rnew, pnew, ga,
+                                      de, rr);
+        else
+            cg2_sweep<U>(g, cr, s, alpha, beta, first, setup, r, pold, x, rnew, pnew, ga, de, rr);
+    };
     // set-up: r0 = b - A x0 with x0 = b (alpha = 1) or x0 = 0 (alpha = 0)
     double part[3] = {0.0, 0.0, 0.0}, tot[3];
-    cg2_sweep<U>(g, cr, s, from_zero ? 0.0 : 1.0, 0.0, true, true, b, nullptr, x, wk.r[0], nullptr, part[0],
-                 part[1], part[2]);
+    sweep(from_zero ? 0.0 : 1.0, 0.0, true, true, b, nullptr, wk.r[0], nullptr, part[0], part[1], part[2]);
     if (!team_reduce_n<3>(tm, part, wk.red, tot)) return -1;
     double gamma = tot[0], delta = tot[1];
     const double bb = tot[2];
@@ -770,8 +931,8 @@ __device__ int cg_team_2d_r(Team &tm, const Geom &g, double s, double tol, int m
     while (it < maxit && gamma > thresh) {
         double pp[2] = {0.0, 0.0}, tt[2];
         double unused = 0.0;
-        cg2_sweep<U>(g, cr, s, alpha, beta, it == 0, false, wk.r[cur], wk.p[cur], x, wk.r[cur ^ 1],
-                     wk.p[cur ^ 1], pp[0], pp[1], unused);
+        sweep(alpha, beta, it == 0, false, wk.r[cur], wk.p[cur], wk.r[cur ^ 1], wk.p[cur ^ 1], pp[0], pp[1],
+              unused);
         if (!team_reduce_n<2>(tm, pp, wk.red, tt)) return -1;
         ++it;
         beta = tt[0] / gamma;
