@@ -25,13 +25,13 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 ASYNC_DEPTH = 4         # fine steps per pass inside the persistent asynchronous kernel (2D)
 
 # Bytes per launch moved between L2 and the memory fabric, from two rocprofv3
-# --pmc runs (FETCH_SIZE scaled by 1.996, WRITE_SIZE by 1.000: the factors a
+# --pmc runs (FETCH_SIZE scaled by 1.993, WRITE_SIZE by 1.000: the factors a
 # plain copy of known size gives), kept in profiles/.  They describe the
 # kernel sources with this digest and are reported as null once those change.
-PROFILED_SOURCES = "7a4ee066597bc6bf"
-PROFILED_TRAFFIC = {"async": 4987.22 + 1818.99,      # GB, one launch
-                    "fine": 0.5611 + 0.4912,          # GB, mean over the sync solve's passes
-                    "sweep": 96.0384 + 85.3332}       # GB, mean over the sync solve's sweeps
+PROFILED_SOURCES = "22a75a8bcee6e377"
+PROFILED_TRAFFIC = {"async": 1910.43 + 1838.79,      # GB, one launch
+                    "fine": 0.5243 + 0.4911,          # GB, mean over the sync solve's passes
+                    "sweep": 82.1465 + 85.2697}       # GB, mean over the sync solve's sweeps
 
 
 def sources_digest():
