@@ -54,7 +54,7 @@ struct BatchArgs {
     unsigned *tctr;
     long long *tbc;
     double *tred;
-    double *wn, *cgr, *cgp0, *cgp1, *d0, *d1;   // [nteams][maxnpts]
+    double *wn, *cgr, *cgr1, *cgp0, *cgp1, *d0, *d1;   // [nteams][maxnpts]
     long long maxnpts;
     const int *order;
     unsigned *queue;
@@ -108,15 +108,23 @@ __global__ __launch_bounds__(BLOCK) void k_bfine_sw(const BProb *__restrict__ pr
     fine2d_sw<XP, D>(src, target(pass), n, P.r, steps, strip / nsy, ya, min(n, ya + ry), (strip % nsy) & 1);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_bsweep(BatchArgs a) {
+// Three workgroups per CU: 96 teams on the chip (11.0 s for the 512-problem
+// batch against 11.9 s with two per CU and the registers the marching CG
+// would take unbounded).
+__global__ __launch_bounds__(BLOCK, 3) void k_bsweep(BatchArgs a) {
     const int team = a.team_of[blockIdx.x];
     if (team < 0) return;
     Team tm{a.tctr + (long long)team * a.ctr_stride, a.ctl, a.tsz, a.rank_of[blockIdx.x], 0u};
     if (!team_setup(tm)) return;
     long long *bc = a.tbc + team * 16;
     double *wn = a.wn + team * a.maxnpts;
-    CGWork wk{a.cgr + team * a.maxnpts, a.cgp0 + team * a.maxnpts, a.cgp1 + team * a.maxnpts,
-              a.tred + (long long)team * 2 * a.tsz};
+    // a team of 8 workgroups sweeps a whole problem: the marching CG
+    CGWork2M wk;
+    wk.r[0] = a.cgr + team * a.maxnpts;
+    wk.r[1] = a.cgr1 + team * a.maxnpts;
+    wk.p[0] = a.cgp0 + team * a.maxnpts;
+    wk.p[1] = a.cgp1 + team * a.maxnpts;
+    wk.red = a.tred + (long long)team * 6 * a.tsz;
     __shared__ double lds[MAX_WAVES];
     const bool leader = (tm.rank == 0 && threadIdx.x == 0);
     for (;;) {
@@ -187,7 +195,7 @@ struct BatchWork {
     int *order = nullptr, *team_of = nullptr, *rank_of = nullptr;
     unsigned *tctr = nullptr, *queue = nullptr;
     long long *tbc = nullptr;
-    double *tred = nullptr, *wn = nullptr, *cgr = nullptr, *cgp0 = nullptr, *cgp1 = nullptr;
+    double *tred = nullptr, *wn = nullptr, *cgr = nullptr, *cgr1 = nullptr, *cgp0 = nullptr, *cgp1 = nullptr;
     double *d0 = nullptr, *d1 = nullptr;
     long long maxnpts = 0, total = 0;
     int nteams = 0, tsz = 0, grid = 0;

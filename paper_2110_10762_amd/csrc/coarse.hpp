@@ -561,6 +561,8 @@ struct CGWork2 {
     double *r[2], *p[2];   // [npts] each
     double *red;           // [6 * team size] reduction slots
 };
+// The same vectors, solved with the marching sweep (cg2_sweep_sw below).
+struct CGWork2M : CGWork2 {};
 
 // A chunk point of the distance-2 star: its index, the addresses of the
 // loads (missing points read the point itself and are masked) and masks.
