@@ -345,13 +345,14 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
         // marching sweep: a team sweeps a whole state with an eighth of the
         // chip or less, so each wave owns a long run of rows and streams it
         // with its loads four rows ahead (1.33x faster than chunks visited
-        // one or two at a time, whose load latency set the pace).  3D: one
-        // chunk per loop trip (the kernel's registers set its occupancy).
+        // one or two at a time, whose load latency set the pace).  3D: the
+        // two-phase CG with four chunks in flight per wave (26.6 s for the 3D
+        // workload with one, 11.7 s with four).
         int it;
         if constexpr (DIM == 2)
             it = cg_team_2d_r<1, true>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk2, abs_thresh2);
         else
-            it = cg_team_dim<DIM, 1>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
+            it = cg_team_dim<DIM, 4>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
         if (it < 0) return -1;
         return team_sync(tm) ? it : -1;
     }

@@ -8,11 +8,11 @@
 //       slice and iteration and are precomputed once on the host).
 //   2D/3D: conjugate gradients started from x0 = b, stopped at
 //       ||r||_2 <= tol ||b||_2, executed by a team of workgroups with
-//       deterministic team reductions.  Teams inside one XCD run the textbook
-//       recurrences (two team barriers per iteration: the search-direction
-//       update is fused into the matrix-vector product); whole-GPU teams,
-//       whose barriers cross the XCDs, run the Chronopoulos-Gear variant with
-//       one barrier per iteration.
+//       deterministic team reductions.  2D: the Chronopoulos-Gear variant
+//       with one barrier per iteration and the products recomputed (48 B per
+//       point and iteration).  3D: the textbook recurrences, two barriers per
+//       iteration, the search-direction update fused into the matrix-vector
+//       product (64 B per point and iteration).
 #pragma once
 #include "common.hpp"
 
@@ -418,136 +418,12 @@ __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int ma
     return it;
 }
 
-// ------------------------------------------------------------------ CG, one synchronisation per iteration
-// The Chronopoulos-Gear form of CG: with w = A r and s = A p carried by
-// recurrences, both inner products of an iteration, (r, r) and (w, r), are
-// reduced together, so an iteration costs one team barrier instead of two.
-// The residual update r' = r - alpha (w + beta s_old) is fused into the next
-// product w' = A r' by recomputing r' at the neighbours from the stored r, w
-// and s_old (identical arithmetic everywhere, so every copy agrees bit for
-// bit); r, w and s are double-buffered because neighbours read the old ones
-// while the new ones are written.  80 B of HBM traffic per point and
-// iteration (reads r, w, s_old, p_old, x; writes s, p, x, r', w').  Same
-// start and stop rules and the same U (chunks per wave and loop trip) as
-// cg_team_dim; the iterates agree with it up to rounding.  For whole-GPU
-// teams, whose barriers span the XCDs.
-struct CGWork1 {
-    double *r[2], *w[2], *s[2], *p;   // [npts] each
-    double *red;                      // [4 * team size] reduction slots
-};
-
-template <int DIM, int U>
-__device__ int cg_team_sync1(Team &tm, const Geom &g, double s, double tol, int maxit,
-                             const double *__restrict__ b, double *__restrict__ x, const CGWork1 &wk,
-                             double abs_thresh2) {
-    constexpr int V = 2 * DIM;
-    const double twod = 2.0 * DIM;
-    const int n = g.n;
-    const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
-    const int wv = wave_id();
-    const long long nw = nwaves();
-    const bool from_zero = abs_thresh2 >= 0.0;
-    int cur = 0;
-
-    // r0 = b - A x0, x = x0 (x0 = b, or 0 for a change of the input)
-    double bb_p = 0.0;
-    for (long long c = cr.begin + wv; c < cr.end; c += nw) {
-        const CPt q = cpt_at(g, c);
-        double v[V];
-        cpt_load<DIM>(q, n, [&](int j) { return b[j]; }, v);
-        double bv;
-        const double ab = cpt_apply<DIM>(q, v, bv, twod, s);
-        if (q.m & CP_VALID) {
-            x[q.c] = from_zero ? 0.0 : bv;
-            wk.r[0][q.c] = from_zero ? bv : bv - ab;
-            bb_p = __builtin_fma(bv, bv, bb_p);
-        }
-    }
-    double bb, unused;
-    if (!team_reduce2(tm, bb_p, 0.0, wk.red, bb, unused)) return -1;
-    // w0 = A r0, gamma = (r0, r0), delta = (w0, r0)
-    double ga_p = 0.0, de_p = 0.0;
-    for (long long c = cr.begin + wv; c < cr.end; c += nw) {
-        const CPt q = cpt_at(g, c);
-        double v[V];
-        cpt_load<DIM>(q, n, [&](int j) { return wk.r[0][j]; }, v);
-        double rv;
-        const double wn = cpt_apply<DIM>(q, v, rv, twod, s);
-        if (q.m & CP_VALID) {
-            wk.w[0][q.c] = wn;
-            ga_p = __builtin_fma(rv, rv, ga_p);
-            de_p = __builtin_fma(wn, rv, de_p);
-        }
-    }
-    double gamma, delta;
-    if (!team_reduce2(tm, ga_p, de_p, wk.red, gamma, delta)) return -1;
-    const double thresh = from_zero ? (abs_thresh2 > 0.0 ? abs_thresh2 : tol * tol * bb) : tol * tol * bb;
-    double alpha = gamma / delta, beta = 0.0;
-    bool first = true;
-    int it = 0;
-    while (it < maxit && gamma > thresh) {
-        const double *ro = wk.r[cur], *wo = wk.w[cur], *so = wk.s[cur];
-        double *rn = wk.r[cur ^ 1], *wn = wk.w[cur ^ 1], *sn = wk.s[cur ^ 1];
-        ga_p = 0.0;
-        de_p = 0.0;
-        for (long long c0 = cr.begin + wv; c0 < cr.end; c0 += U * nw) {
-            CPt q[U];
-            bool act[U];
-            double rv[U][V], wvv[U][V], sv[U][V], pold[U], xold[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const long long c = c0 + u * nw;
-                act[u] = c < cr.end;
-                q[u] = cpt_at(g, act[u] ? c : c0);
-                cpt_load<DIM>(q[u], n, [&](int j) { return ro[j]; }, rv[u]);
-                cpt_load<DIM>(q[u], n, [&](int j) { return wo[j]; }, wvv[u]);
-                if (first) {
-#pragma unroll
-                    for (int k = 0; k < V; ++k) sv[u][k] = 0.0;
-                    pold[u] = 0.0;
-                } else {
-                    cpt_load<DIM>(q[u], n, [&](int j) { return so[j]; }, sv[u]);
-                    pold[u] = wk.p[q[u].c];
-                }
-                xold[u] = x[q[u].c];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                double rnv[V];   // r' at the point and its neighbours
-#pragma unroll
-                for (int k = 0; k < V; ++k)
-                    rnv[k] = __builtin_fma(-alpha, __builtin_fma(beta, sv[u][k], wvv[u][k]), rv[u][k]);
-                double rc;
-                const double wnew = cpt_apply<DIM>(q[u], rnv, rc, twod, s);
-                if (act[u] && (q[u].m & CP_VALID)) {
-                    const int i = q[u].c;
-                    const double pc = __builtin_fma(beta, pold[u], rv[u][0]);
-                    sn[i] = __builtin_fma(beta, sv[u][0], wvv[u][0]);
-                    wk.p[i] = pc;
-                    x[i] = __builtin_fma(alpha, pc, xold[u]);
-                    rn[i] = rc;
-                    wn[i] = wnew;
-                    ga_p = __builtin_fma(rc, rc, ga_p);
-                    de_p = __builtin_fma(wnew, rc, de_p);
-                }
-            }
-        }
-        double gnew, dnew;
-        if (!team_reduce2(tm, ga_p, de_p, wk.red, gnew, dnew)) return -1;
-        ++it;
-        beta = gnew / gamma;
-        alpha = gnew / (dnew - beta * gnew / alpha);
-        gamma = gnew;
-        cur ^= 1;
-        first = false;
-    }
-    return it;
-}
-
-// ------------------------------------------------------------------ 2D CG, products recomputed
-// The one-synchronisation CG above with neither w = A r nor s = A p stored:
-// a wave recomputes A p at the point and its four neighbours from p (hence
-// p at distance 2), updates r there, and forms w' = A r' at the point.
+// ------------------------------------------------------------------ 2D CG, one synchronisation per iteration
+// The Chronopoulos-Gear form of CG: with w = A r and s = A p, both inner
+// products of an iteration, (r, r) and (w, r), can be reduced together, so an
+// iteration costs one team barrier instead of two.  Neither w nor s is
+// stored: a wave recomputes A p at the point and its four neighbours from p
+// (hence p at distance 2), updates r there, and forms w' = A r' at the point.
 // Stored state: x, r, p (r and p double-buffered), 48 B of HBM traffic per
 // point and iteration; the extra reads of the distance-2 rows hit the
 // caches.  Iteration i:

@@ -116,7 +116,7 @@ struct pr_problem {
     // synchronous workspace (single problem)
     double *v = nullptr, *w = nullptr, *tmp = nullptr, *wn = nullptr, *d0 = nullptr, *d1 = nullptr;
     double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *red = nullptr;
-    double *cg1[4] = {nullptr, nullptr, nullptr, nullptr};   // extra vectors of the one-synchronisation CG
+    double *cg_r1 = nullptr;   // second residual buffer of the 2D one-synchronisation CG
     double *inv_tab = nullptr;        // 1D Thomas factors, padded
     double *inv_tab_f = nullptr;      // 1D Thomas factors of an implicit fine step (s = theta r)
     // implicit fine steps on many states (2D/3D): per-team tmp, rhs, CG set
@@ -489,8 +489,7 @@ static SweepArgs sweep_args(pr_problem *h, const Prob &P, double *lam) {
     a.cg_tol = P.cg_tol;
     a.cg_maxit = P.cg_maxit;
     a.wk = CGWork{h->cg_r, h->cg_p0, h->cg_p1, h->red};
-    a.wk1 = CGWork1{{h->cg_r, h->cg_p0}, {h->cg_p1, h->cg1[0]}, {h->cg1[1], h->cg1[2]}, h->cg1[3], h->red};
-    a.wk2 = CGWork2{{h->cg_r, h->cg_p0}, {h->cg_p1, h->cg1[0]}, h->red};
+    a.wk2 = CGWork2{{h->cg_r, h->cg_r1}, {h->cg_p0, h->cg_p1}, h->red};
     a.ctr = h->ctr;
     a.ctl = h->ctl;
     return a;
@@ -536,8 +535,7 @@ static int alloc_sync(pr_problem *h) {
         if ((rc = alloc_t(h, &h->cg_r, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_p0, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_p1, P.npts))) return rc;
-        for (auto &v : h->cg1)
-            if ((rc = alloc_t(h, &v, P.npts))) return rc;
+        if ((rc = alloc_t(h, &h->cg_r1, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->d0, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->d1, P.npts))) return rc;
     }

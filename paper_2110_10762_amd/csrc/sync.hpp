@@ -40,8 +40,7 @@ struct SweepArgs {
     double cg_tol;
     int cg_maxit;
     CGWork wk;
-    CGWork1 wk1;        // whole-GPU sweeps: one-synchronisation CG (3D)
-    CGWork2 wk2;        //                   and with recomputed products (2D)
+    CGWork2 wk2;        // 2D: one-synchronisation CG, products recomputed
     unsigned *ctr;
     Control *ctl;
 };
@@ -119,12 +118,10 @@ struct SweepBufs {
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWork &wk, double abs_thresh2) {
-    return cg_team_dim<DIM, DIM == 3 ? 1 : 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
-}
-template <int DIM>
-__device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
-                                       const double *b, double *x, const CGWork1 &wk, double abs_thresh2) {
-    return cg_team_sync1<DIM, DIM == 3 ? 1 : 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+    // 3D whole-GPU sweep: two chunks in flight per wave (8.7 s for the 3D
+    // workload against 9.0 s with one; the one-synchronisation form with w
+    // and s stored moves 80 B per point and took 10.9 s)
+    return cg_team_dim<DIM, 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
 
 template <int DIM>
@@ -217,7 +214,7 @@ __global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
                                   a.incr != 0, B, a.wk2, dmax, its, lds);
     else
         ok = team_coarse_sweep<3>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
-                                  a.incr != 0, B, a.wk1, dmax, its, lds);
+                                  a.incr != 0, B, a.wk, dmax, its, lds);
     if (!ok) return;
     dmax = block_reduce<true>(dmax, lds);
     if (threadIdx.x == 0) {

@@ -88,8 +88,11 @@ def test_replay_random_schedule_1d(seed, delay):
     assert rel(lam, ref.current()) <= TOL
 
 
-def test_replay_random_schedule_2d():
-    p = workloads.heat2d(n=47, nslices=6, T=1e-2)
+@pytest.mark.parametrize("n", [47, 130])
+def test_replay_random_schedule_2d(n):
+    # n = 130: three column strips of the coarse solver's marching sweep, the
+    # last one ragged (2 columns), so the strip-border neighbours are exercised
+    p = workloads.heat2d(n=n, nslices=6, T=1e-2)
     d = disc_of(p)
     props = heat.Propagators(d, cg_tol=p.cg_tol)
     ref = parareal.run_random(p.u0, props.F, props.G, d.nslices, seed=11, max_delay=2, max_rounds=5)
@@ -147,6 +150,18 @@ def test_free_mode_reaches_fixed_point(which, teams):
     # that presumes a predecessor is never ahead of the synchronous schedule,
     # which a team holding a block of slices can be: kappa < k is observed.)
     assert all(1 <= k <= 4 * d.nslices + 16 for k in st.k_per_slice)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 65])
+def test_free_mode_2d_small_and_ragged_grids(n):
+    # degenerate grids (one to three points a side: every neighbour of a row
+    # is missing or a boundary) and one just past a column strip (65 = 64 + 1)
+    p = workloads.heat2d(n=n, nslices=5, T=1e-2)
+    d = disc_of(p)
+    prob, lam, st = solve(p, pr.PR_ASYNC_FREE)
+    assert st.converged == 1
+    star = heat.serial_fine(p.u0, d.r, d.m, d.nslices)
+    assert rel(lam, star) <= TOL
 
 
 def test_free_mode_with_injected_delays_1d():
