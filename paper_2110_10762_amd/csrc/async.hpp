@@ -249,7 +249,7 @@ __device__ __forceinline__ void team_copy(const Team &tm, const Geom &g, const d
 // explicit kernel carries none of their registers).
 template <int DIM, int XP, int RR, int D, bool IMPL>
 __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const double *src, double *dst, double *scr,
-                          const CGWork &wk, double *rhs, unsigned long long &fine_its) {
+                          const CGWork &wk, const CGWork2 &wk2, double *rhs, unsigned long long &fine_its) {
     if constexpr (IMPL) {   // implicit theta-steps: Thomas per wave (1D), team CG
         if constexpr (DIM == 1) {
             if (wave_id() == 0) {
@@ -262,8 +262,8 @@ __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const do
             }
             return team_sync(tm);
         } else {
-            const long long it = team_fine_theta<DIM, 1>(tm, a.g, a.fine_kind, a.r, a.m, a.cg_tol, a.cg_maxit,
-                                                          src, dst, scr, rhs, wk);
+            const long long it = team_fine_theta<DIM, 2, true>(tm, a.g, a.fine_kind, a.r, a.m, a.cg_tol, a.cg_maxit,
+                                                          src, dst, scr, rhs, wk, wk2);
             if (it < 0) return false;
             fine_its += (unsigned long long)it;
             return true;
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
             double *v = a.V + i * np;
             // ---------------- v = F(x_old)
             tp = wall_clock64();
-            if (!team_fine<DIM, XP, RR, D, IMPL>(tm, a, x_old, v, a.S ? a.S + i * np : nullptr, wk,
+            if (!team_fine<DIM, XP, RR, D, IMPL>(tm, a, x_old, v, a.S ? a.S + i * np : nullptr, wk, wk2,
                                            a.cgb ? a.cgb + (long long)team * a.cgs : nullptr, fine_its))
                 goto out;
             {   // uniform code: the phase clocks stay in scalar registers

@@ -64,10 +64,14 @@ __device__ bool team_apply_be(Team &tm, const Geom &g, double s, const double *_
 // `steps` theta-steps of one state by the team, src -> dst, ping-pong through
 // tmp so that the last step lands in dst (src is never written); rhs holds the
 // trapezoidal right-hand side.  Returns the CG iterations, or -1 if aborted.
-template <int DIM, int U>
+// 2D solves take the one-synchronisation CG (wk2): marching when the team's
+// waves each get 16 rows of a column strip or more, chunk-wise otherwise (a
+// team spanning the whole GPU); ALWAYS_MARCH keeps only the marching form
+// (teams of an XCD or less).  3D solves take the two-phase CG (wk).
+template <int DIM, int U, bool ALWAYS_MARCH = false>
 __device__ __forceinline__ long long team_fine_theta(Team &tm, const Geom &g, int kind, double r, int steps, double tol,
                                      int maxit, const double *src, double *dst, double *tmp, double *rhs,
-                                     const CGWork &wk) {
+                                     const CGWork &wk, const CGWork2 &wk2) {
     const double th = theta_of(kind);
     long long its = 0;
     const double *cur = src;
@@ -78,7 +82,15 @@ __device__ __forceinline__ long long team_fine_theta(Team &tm, const Geom &g, in
             if (!team_apply_be<DIM>(tm, g, -(1.0 - th) * r, cur, rhs)) return -1;
             b = rhs;
         }
-        const int it = cg_team_dim<DIM, U>(tm, g, th * r, tol, maxit, b, tgt, wk, -1.0);
+        int it;
+        if constexpr (DIM == 2) {
+            if (ALWAYS_MARCH || (long long)g.n * g.cpr >= 16LL * tm.size * nwaves())
+                it = cg_team_2d_r<1, true>(tm, g, th * r, tol, maxit, b, tgt, wk2, -1.0);
+            else
+                it = cg_team_2d_r<1, false>(tm, g, th * r, tol, maxit, b, tgt, wk2, -1.0);
+        } else {
+            it = cg_team_dim<DIM, U>(tm, g, th * r, tol, maxit, b, tgt, wk, -1.0);
+        }
         if (it < 0 || !team_sync(tm)) return -1;
         its += it;
         cur = tgt;
@@ -89,7 +101,8 @@ __device__ __forceinline__ long long team_fine_theta(Team &tm, const Geom &g, in
 // Many states (the synchronous driver's fine sweep, serial runs): one team per
 // group of workgroups with equal blockIdx modulo nteams (nteams divides 8, so
 // a team stays on the XCDs dispatch gives those blocks); team t takes states
-// t, t + nteams, ...  Per team: tmp, rhs and a CG set at `stride` apart.
+// t, t + nteams, ...  Per team: tmp, rhs and four CG vectors at `stride`
+// apart, and 6 * size reduction slots.
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_fine_theta(const double *src, double *dst, long long sstride,
                                                       long long dstride, int count, Geom g, int kind, double r,
@@ -100,13 +113,15 @@ __global__ __launch_bounds__(BLOCK) void k_fine_theta(const double *src, double 
     const int size = gridDim.x / nteams;
     Team tm{ctr + (long long)team * team_counter_words(0), ctl, size, (int)blockIdx.x / nteams, 0u};
     if (!team_setup(tm)) return;
-    double *base = scr + (long long)team * 5 * stride;
-    const CGWork wk{base + 2 * stride, base + 3 * stride, base + 4 * stride, red + (long long)team * 2 * size};
+    double *base = scr + (long long)team * 6 * stride;
+    double *tred = red + (long long)team * 6 * size;
+    const CGWork wk{base + 2 * stride, base + 3 * stride, base + 4 * stride, tred};
+    const CGWork2 wk2{{base + 2 * stride, base + 5 * stride}, {base + 3 * stride, base + 4 * stride}, tred};
     unsigned long long its = 0;
     for (int c = team; c < count; c += nteams) {
-        const long long it = team_fine_theta<DIM, DIM == 3 ? 1 : 2>(tm, g, kind, r, steps, tol, maxit,
+        const long long it = team_fine_theta<DIM, DIM == 3 ? 4 : 2>(tm, g, kind, r, steps, tol, maxit,
                                                                    src + c * sstride, dst + c * dstride, base,
-                                                                   base + stride, wk);
+                                                                   base + stride, wk, wk2);
         if (it < 0) return;
         its += (unsigned long long)it;
     }

@@ -435,8 +435,8 @@ static int run_fine_theta(pr_problem *h, const Prob &P, const double *src, doubl
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, BLOCK, 0));
         if (occ < 1) return fail(PR_ENORESIDENT, "implicit fine kernel cannot be resident");
         h->fth_grid = (h->ncu * std::min(occ, 4)) / kXcds * kXcds;
-        if ((rc = alloc_t(h, &h->fth_scr, (size_t)kXcds * 5 * stride))) return rc;
-        if ((rc = alloc_t(h, &h->fth_red, (size_t)2 * h->fth_grid))) return rc;
+        if ((rc = alloc_t(h, &h->fth_scr, (size_t)kXcds * 6 * stride))) return rc;
+        if ((rc = alloc_t(h, &h->fth_red, (size_t)6 * h->fth_grid))) return rc;
         if ((rc = alloc_t(h, &h->fth_ctr, (size_t)kXcds * team_counter_words(0)))) return rc;
         if ((rc = alloc_t(h, &h->fth_its, 1))) return rc;
         if ((rc = zero_words(h, h->fth_its, 2))) return rc;
