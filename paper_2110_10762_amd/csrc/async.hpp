@@ -350,7 +350,7 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
         // workload with one, 11.7 s with four).
         int it;
         if constexpr (DIM == 2)
-            it = cg_team_2d_r<1, true>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk2, abs_thresh2);
+            it = cg_team_2d_r<true>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk2, abs_thresh2);
         else
             it = cg_team_dim<DIM, 4>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
         if (it < 0) return -1;

@@ -556,71 +556,94 @@ __device__ __forceinline__ Star13 d2_star(const D2Pt &q, const Raw9 &w) {
 // (zero outside the domain), w' = A r' at the point; stores x + alpha p, r'
 // and (unless `setup`) p; accumulates (r', r'), (w', r') and (r, r).
 // At set-up r is the right-hand side b, first is set and x is taken as 0.
-template <int U>
+// The loads of a wave's first chunk of a sweep, issued early: between the
+// barrier that ends an iteration and the reading of the reduction slots,
+// whose round trip they then overlap.
+struct Cg2Pre {
+    D2Pt q;
+    Raw9 wr, wp;
+    double xo;
+    bool ok;   // the wave has a chunk
+};
+
+__device__ __forceinline__ void cg2_preload(const Geom &g, const ChunkRange &cr, bool first, bool setup,
+                                            const double *__restrict__ r, const double *__restrict__ pold,
+                                            const double *__restrict__ x, Cg2Pre &pre) {
+    const long long c = cr.begin + wave_id();
+    pre.ok = c < cr.end;
+    if (!pre.ok) return;
+    pre.q = d2_at(g, c);
+    d2_load(pre.q, r, pre.wr);
+    if (!first) d2_load(pre.q, pold, pre.wp);
+    pre.xo = setup ? 0.0 : x[pre.q.c];
+}
+
+// One sweep, one chunk per wave and loop trip; the first chunk's loads come
+// from `pre` when it holds them.
+__device__ __forceinline__ void cg2_chunk(const D2Pt &q, const Raw9 &wr, const Raw9 &wp, double xo, double s,
+                                          double alpha, double beta, bool first, bool setup,
+                                          double *__restrict__ x, double *__restrict__ rnew,
+                                          double *__restrict__ pnew, double &ga, double &de, double &rr) {
+    const Star13 R = d2_star(q, wr);
+    Star13 P = R;
+    if (!first) {
+        const Star13 Po = d2_star(q, wp);
+        P.c = __builtin_fma(beta, Po.c, R.c);
+        P.l1 = __builtin_fma(beta, Po.l1, R.l1);
+        P.l2 = __builtin_fma(beta, Po.l2, R.l2);
+        P.r1 = __builtin_fma(beta, Po.r1, R.r1);
+        P.r2 = __builtin_fma(beta, Po.r2, R.r2);
+        P.u = __builtin_fma(beta, Po.u, R.u);
+        P.ul = __builtin_fma(beta, Po.ul, R.ul);
+        P.ur = __builtin_fma(beta, Po.ur, R.ur);
+        P.d = __builtin_fma(beta, Po.d, R.d);
+        P.dl = __builtin_fma(beta, Po.dl, R.dl);
+        P.dr = __builtin_fma(beta, Po.dr, R.dr);
+        P.uu = __builtin_fma(beta, Po.uu, R.uu);
+        P.dd = __builtin_fma(beta, Po.dd, R.dd);
+    }
+    // A p at the point and its neighbours: (up + down) + (left + right)
+    const double ap_c = be_point(P.c, (P.u + P.d) + (P.l1 + P.r1), 4.0, s);
+    const double ap_l = be_point(P.l1, (P.ul + P.dl) + (P.l2 + P.c), 4.0, s);
+    const double ap_r = be_point(P.r1, (P.ur + P.dr) + (P.c + P.r2), 4.0, s);
+    const double ap_u = be_point(P.u, (P.uu + P.c) + (P.ul + P.ur), 4.0, s);
+    const double ap_d = be_point(P.d, (P.c + P.dd) + (P.dl + P.dr), 4.0, s);
+    const unsigned m = q.m;
+    const double rc = (m & D2_V) ? __builtin_fma(-alpha, ap_c, R.c) : 0.0;
+    const double rl = (m & D2_XL) ? __builtin_fma(-alpha, ap_l, R.l1) : 0.0;
+    const double rrt = (m & D2_XR) ? __builtin_fma(-alpha, ap_r, R.r1) : 0.0;
+    const double ru = (m & D2_U) ? __builtin_fma(-alpha, ap_u, R.u) : 0.0;
+    const double rd = (m & D2_D) ? __builtin_fma(-alpha, ap_d, R.d) : 0.0;
+    const double wn = be_point(rc, (ru + rd) + (rl + rrt), 4.0, s);
+    if (m & D2_V) {
+        const int i = q.c;
+        x[i] = __builtin_fma(alpha, P.c, xo);
+        rnew[i] = rc;
+        if (!setup) pnew[i] = P.c;
+        ga = __builtin_fma(rc, rc, ga);
+        de = __builtin_fma(wn, rc, de);
+        rr = __builtin_fma(R.c, R.c, rr);
+    }
+}
+
 __device__ __forceinline__ void cg2_sweep(const Geom &g, const ChunkRange &cr, double s, double alpha, double beta,
                                           bool first, bool setup, const double *__restrict__ r,
                                           const double *__restrict__ pold, double *__restrict__ x,
                                           double *__restrict__ rnew, double *__restrict__ pnew, double &ga,
-                                          double &de, double &rr) {
-    const int wv = wave_id();
+                                          double &de, double &rr, const Cg2Pre *pre) {
     const long long nw = nwaves();
-    for (long long c0 = cr.begin + wv; c0 < cr.end; c0 += U * nw) {
-        D2Pt q[U];
-        bool act[U];
-        Raw9 wr[U], wp[U];
-        double xo[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const long long c = c0 + u * nw;
-            act[u] = c < cr.end;
-            q[u] = d2_at(g, act[u] ? c : c0);
-            d2_load(q[u], r, wr[u]);
-            if (!first) d2_load(q[u], pold, wp[u]);
-            xo[u] = setup ? 0.0 : x[q[u].c];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const Star13 R = d2_star(q[u], wr[u]);
-            Star13 P = R;
-            if (!first) {
-                const Star13 Po = d2_star(q[u], wp[u]);
-                P.c = __builtin_fma(beta, Po.c, R.c);
-                P.l1 = __builtin_fma(beta, Po.l1, R.l1);
-                P.l2 = __builtin_fma(beta, Po.l2, R.l2);
-                P.r1 = __builtin_fma(beta, Po.r1, R.r1);
-                P.r2 = __builtin_fma(beta, Po.r2, R.r2);
-                P.u = __builtin_fma(beta, Po.u, R.u);
-                P.ul = __builtin_fma(beta, Po.ul, R.ul);
-                P.ur = __builtin_fma(beta, Po.ur, R.ur);
-                P.d = __builtin_fma(beta, Po.d, R.d);
-                P.dl = __builtin_fma(beta, Po.dl, R.dl);
-                P.dr = __builtin_fma(beta, Po.dr, R.dr);
-                P.uu = __builtin_fma(beta, Po.uu, R.uu);
-                P.dd = __builtin_fma(beta, Po.dd, R.dd);
-            }
-            // A p at the point and its neighbours: (up + down) + (left + right)
-            const double ap_c = be_point(P.c, (P.u + P.d) + (P.l1 + P.r1), 4.0, s);
-            const double ap_l = be_point(P.l1, (P.ul + P.dl) + (P.l2 + P.c), 4.0, s);
-            const double ap_r = be_point(P.r1, (P.ur + P.dr) + (P.c + P.r2), 4.0, s);
-            const double ap_u = be_point(P.u, (P.uu + P.c) + (P.ul + P.ur), 4.0, s);
-            const double ap_d = be_point(P.d, (P.c + P.dd) + (P.dl + P.dr), 4.0, s);
-            const unsigned m = q[u].m;
-            const double rc = (m & D2_V) ? __builtin_fma(-alpha, ap_c, R.c) : 0.0;
-            const double rl = (m & D2_XL) ? __builtin_fma(-alpha, ap_l, R.l1) : 0.0;
-            const double rrt = (m & D2_XR) ? __builtin_fma(-alpha, ap_r, R.r1) : 0.0;
-            const double ru = (m & D2_U) ? __builtin_fma(-alpha, ap_u, R.u) : 0.0;
-            const double rd = (m & D2_D) ? __builtin_fma(-alpha, ap_d, R.d) : 0.0;
-            const double wn = be_point(rc, (ru + rd) + (rl + rrt), 4.0, s);
-            if (act[u] && (m & D2_V)) {
-                const int i = q[u].c;
-                x[i] = __builtin_fma(alpha, P.c, xo[u]);
-                rnew[i] = rc;
-                if (!setup) pnew[i] = P.c;
-                ga = __builtin_fma(rc, rc, ga);
-                de = __builtin_fma(wn, rc, de);
-                rr = __builtin_fma(R.c, R.c, rr);
-            }
-        }
+    long long c = cr.begin + wave_id();
+    if (pre && pre->ok) {
+        cg2_chunk(pre->q, pre->wr, pre->wp, pre->xo, s, alpha, beta, first, setup, x, rnew, pnew, ga, de, rr);
+        c += nw;
+    }
+    for (; c < cr.end; c += nw) {
+        const D2Pt q = d2_at(g, c);
+        Raw9 wr, wp;
+        d2_load(q, r, wr);
+        if (!first) d2_load(q, pold, wp);
+        const double xo = setup ? 0.0 : x[q.c];
+        cg2_chunk(q, wr, wp, xo, s, alpha, beta, first, setup, x, rnew, pnew, ga, de, rr);
     }
 }
 
@@ -781,25 +804,32 @@ __device__ __forceinline__ void cg2_sweep_sw(const Geom &g, int rank, int size, 
 // cg_team_dim (abs_thresh2 < 0: x0 = b, relative stop; >= 0: x0 = 0,
 // absolute stop).  Returns the iteration count, or -1 if the launch was
 // aborted.  x must not alias b or the work vectors.
-// SW: the marching sweep (teams that own a whole state with few waves).
-template <int U, bool SW = false, int SWSEG = 16, int SWPF = 4>
+// SW: the marching sweep (teams that own a whole state with few waves);
+// otherwise chunk-wise, with each wave's first chunk of the next sweep loaded
+// while the reduction slots are read.
+template <bool SW = false, int SWSEG = 16, int SWPF = 4>
 __device__ int cg_team_2d_r(Team &tm, const Geom &g, double s, double tol, int maxit,
                             const double *__restrict__ b, double *__restrict__ x, const CGWork2 &wk,
                             double abs_thresh2) {
     const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
     const bool from_zero = abs_thresh2 >= 0.0;
+    Cg2Pre pre;
     auto sweep = [&](double alpha, double beta, bool first, bool setup, const double *r, const double *pold,
                      double *rnew, double *pnew, double &ga, double &de, double &rr) {
         if constexpr (SW)
             cg2_sweep_sw<SWPF, SWSEG>(g, tm.rank, tm.size, s, alpha, beta, first, setup, r, pold, x, rnew, pnew, ga,
                                       de, rr);
         else
-            cg2_sweep<U>(g, cr, s, alpha, beta, first, setup, r, pold, x, rnew, pnew, ga, de, rr);
+            cg2_sweep(g, cr, s, alpha, beta, first, setup, r, pold, x, rnew, pnew, ga, de, rr,
+                      setup ? nullptr : &pre);
     };
     // set-up: r0 = b - A x0 with x0 = b (alpha = 1) or x0 = 0 (alpha = 0)
     double part[3] = {0.0, 0.0, 0.0}, tot[3];
     sweep(from_zero ? 0.0 : 1.0, 0.0, true, true, b, nullptr, wk.r[0], nullptr, part[0], part[1], part[2]);
-    if (!team_reduce_n<3>(tm, part, wk.red, tot)) return -1;
+    int q = team_reduce_begin<3>(tm, part, wk.red);
+    if (q < 0) return -1;
+    if constexpr (!SW) cg2_preload(g, cr, true, false, wk.r[0], nullptr, x, pre);
+    team_reduce_end<3>(tm, wk.red, q, tot);
     double gamma = tot[0], delta = tot[1];
     const double bb = tot[2];
     const double thresh = from_zero ? (abs_thresh2 > 0.0 ? abs_thresh2 : tol * tol * bb) : tol * tol * bb;
@@ -811,7 +841,12 @@ __device__ int cg_team_2d_r(Team &tm, const Geom &g, double s, double tol, int m
         double unused = 0.0;
         sweep(alpha, beta, it == 0, false, wk.r[cur], wk.p[cur], wk.r[cur ^ 1], wk.p[cur ^ 1], pp[0], pp[1],
               unused);
-        if (!team_reduce_n<2>(tm, pp, wk.red, tt)) return -1;
+        q = team_reduce_begin<2>(tm, pp, wk.red);
+        if (q < 0) return -1;
+        // the next sweep reads the vectors just written (p is read from the
+        // second iteration on)
+        if constexpr (!SW) cg2_preload(g, cr, false, false, wk.r[cur ^ 1], wk.p[cur ^ 1], x, pre);
+        team_reduce_end<2>(tm, wk.red, q, tt);
         ++it;
         beta = tt[0] / gamma;
         alpha = tt[0] / (tt[1] - beta * tt[0] / alpha);

@@ -331,8 +331,13 @@ __device__ __forceinline__ bool team_reduce(Team &tm, double part, double *base,
 // size), so set q of one call never meets set 1 - q of the next, whichever
 // of team_reduce and team_reduce_n makes it.  Per value, the order of the
 // additions is that of team_reduce.
+//
+// Split form, for callers that issue loads while the partials travel:
+// team_reduce_begin writes this workgroup's partials and passes the barrier
+// (returns the slot set, or -1 if the launch was aborted); team_reduce_end
+// sums the slots.  No slot write of the team may come in between.
 template <int K>
-__device__ __forceinline__ bool team_reduce_n(Team &tm, const double (&part)[K], double *base, double (&out)[K]) {
+__device__ __forceinline__ int team_reduce_begin(Team &tm, const double (&part)[K], double *base) {
     __shared__ double sl[MAX_WAVES * K];
     const int q = tm.rpar;
     tm.rpar ^= 1;
@@ -355,7 +360,12 @@ __device__ __forceinline__ bool team_reduce_n(Team &tm, const double (&part)[K],
             base[(long long)(2 * k + q) * tm.size + tm.rank] = t;
         }
     }
-    if (!team_sync(tm)) return false;
+    return team_sync(tm) ? q : -1;
+}
+
+template <int K>
+__device__ __forceinline__ void team_reduce_end(const Team &tm, const double *base, int q, double (&out)[K]) {
+    __shared__ double so[K];
     if (threadIdx.x < WAVE) {
         double acc[K];
 #pragma unroll
@@ -377,13 +387,20 @@ __device__ __forceinline__ bool team_reduce_n(Team &tm, const double (&part)[K],
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const double r = wave_sum(acc[k]);
-            if (threadIdx.x == 0) sl[k] = r;
+            if (threadIdx.x == 0) so[k] = r;
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = uniform(sl[k]);
+    for (int k = 0; k < K; ++k) out[k] = uniform(so[k]);
     __syncthreads();
+}
+
+template <int K>
+__device__ __forceinline__ bool team_reduce_n(Team &tm, const double (&part)[K], double *base, double (&out)[K]) {
+    const int q = team_reduce_begin<K>(tm, part, base);
+    if (q < 0) return false;
+    team_reduce_end<K>(tm, base, q, out);
     return true;
 }
 

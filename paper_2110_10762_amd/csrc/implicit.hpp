@@ -85,9 +85,9 @@ __device__ __forceinline__ long long team_fine_theta(Team &tm, const Geom &g, in
         int it;
         if constexpr (DIM == 2) {
             if (ALWAYS_MARCH || (long long)g.n * g.cpr >= 16LL * tm.size * nwaves())
-                it = cg_team_2d_r<1, true>(tm, g, th * r, tol, maxit, b, tgt, wk2, -1.0);
+                it = cg_team_2d_r<true>(tm, g, th * r, tol, maxit, b, tgt, wk2, -1.0);
             else
-                it = cg_team_2d_r<1, false>(tm, g, th * r, tol, maxit, b, tgt, wk2, -1.0);
+                it = cg_team_2d_r<false>(tm, g, th * r, tol, maxit, b, tgt, wk2, -1.0);
         } else {
             it = cg_team_dim<DIM, U>(tm, g, th * r, tol, maxit, b, tgt, wk, -1.0);
         }

@@ -82,7 +82,7 @@ static int r1d_for(int n) {   // registers per lane for a 1D state
     return R;
 }
 static const int kMax1D = 32 * WAVE;   // 2048 points
-static const int SWEEP_BLOCK = 1024;   // threads per workgroup of the whole-GPU coarse sweeps
+static const int SWEEP_BLOCK = SWEEP_THREADS;   // threads per workgroup of the whole-GPU coarse sweeps
 static const int kXcds = 8;            // MI355X: accelerator complex dies (each with its own L2)
 
 // ------------------------------------------------------------------ handle

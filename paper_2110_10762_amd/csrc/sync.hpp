@@ -130,14 +130,14 @@ __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double
     static_assert(DIM == 2, "the recomputing CG is two-dimensional");
     // the whole GPU has more waves than a state has rows per column strip:
     // every wave takes a few chunks (the marching sweep measured 1.6x slower)
-    return cg_team_2d_r<1, false>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+    return cg_team_2d_r<false>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
 
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWork2M &wk, double abs_thresh2) {
     static_assert(DIM == 2, "the recomputing CG is two-dimensional");
-    return cg_team_2d_r<1, true>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+    return cg_team_2d_r<true>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
 
 template <int DIM, typename WK>
@@ -200,8 +200,12 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
 
 // Cooperative launch: the whole grid is one team.
 // one instantiation per dimension (2, 3): each kernel holds one solver copy
+// 768 threads: 168 registers per lane hold the 2D solver with its preloaded
+// chunk (1.16 s for the 1024^2, 64-slice sync solve; 1024 threads spill at
+// 128 registers, 1.53 s, and 512 threads take 1.26 s)
+constexpr int SWEEP_THREADS = 768;
 template <int DIM>
-__global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
+__global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_cg(SweepArgs a) {
     Team tm{a.ctr, a.ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
     if (!team_setup(tm, true)) return;
     __shared__ double lds[MAX_WAVES];
@@ -227,7 +231,7 @@ __global__ __launch_bounds__(1024) void k_sweep_cg(SweepArgs a) {
 // Batch of independent coarse solves (tests and the apply entry point):
 // state c of the batch is solved by the whole grid, one after the other.
 template <int DIM>
-__global__ __launch_bounds__(1024) void k_coarse_cg_batch(const double *src, double *dst, long long npts,
+__global__ __launch_bounds__(SWEEP_THREADS) void k_coarse_cg_batch(const double *src, double *dst, long long npts,
                                                            int count, Geom g, double s, double tol,
                                                            int maxit, CGWork wk, unsigned *ctr,
                                                            Control *ctl, unsigned long long *cg_iters) {
