@@ -856,11 +856,4 @@ __device__ int cg_team_2d_r(Team &tm, const Geom &g, double s, double tol, int m
     return it;
 }
 
-__device__ __forceinline__ int cg_team(Team &tm, const Geom &g, double s, double tol, int maxit,
-                                       const double *__restrict__ b, double *__restrict__ x, const CGWork &wk,
-                                       double abs_thresh2 = -1.0) {
-    if (g.dim == 3) return cg_team_dim<3, 1>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
-    return cg_team_dim<2, 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
-}
-
 }  // namespace pr

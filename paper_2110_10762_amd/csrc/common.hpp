@@ -404,13 +404,4 @@ __device__ __forceinline__ bool team_reduce_n(Team &tm, const double (&part)[K],
     return true;
 }
 
-__device__ __forceinline__ bool team_reduce2(Team &tm, double a, double b, double *base, double &oa, double &ob) {
-    const double part[2] = {a, b};
-    double out[2];
-    if (!team_reduce_n<2>(tm, part, base, out)) return false;
-    oa = out[0];
-    ob = out[1];
-    return true;
-}
-
 }  // namespace pr
