@@ -346,13 +346,13 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
         // chip or less, so each wave owns a long run of rows and streams it
         // with its loads four rows ahead (1.33x faster than chunks visited
         // one or two at a time, whose load latency set the pace).  3D: the
-        // two-phase CG with four chunks in flight per wave (26.6 s for the 3D
-        // workload with one, 11.7 s with four).
+        // two-phase CG with marching phases (26.6 s for the 3D workload with
+        // one chunk per wave in flight, 11.7 s with four, 10.7 s marching).
         int it;
         if constexpr (DIM == 2)
             it = cg_team_2d_r<true>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk2, abs_thresh2);
         else
-            it = cg_team_dim<DIM, 4>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
+            it = cg_team_dim<DIM, 4, DIM == 3>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
         if (it < 0) return -1;
         return team_sync(tm) ? it : -1;
     }

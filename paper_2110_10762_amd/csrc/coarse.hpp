@@ -271,6 +271,151 @@ __device__ __forceinline__ double cpt_apply(const CPt &q, const double (&v)[2 * 
     return be_point(center, s2 + (xl + xr), twod, s);
 }
 
+// ------------------------------------------------------------------ 3D CG phases, marching
+// The phases of the two-phase CG below for a team whose waves each own a long
+// run of rows: a wave takes a strip of 64 x-values in one z-plane and a
+// segment of y-rows and marches down it, keeping three rows of the stencil
+// operand in registers and loading, PF rows ahead, the next row of its plane
+// and the two rows beside the output row in the planes z - 1 and z + 1.  The
+// operand v and the stores per mode:
+//   CG3_A: v = r + beta p_old (r when `first`); p = v, sum v.(A v);
+//   CG3_B: v = p; x += alpha v, r -= alpha A v (in place), sum r.r;
+//   CG3_S: v = b (set-up with x0 = b); x = b, r = b - A b, sums r.r and b.b.
+// A v is formed exactly as in the chunk-wise phases (cpt_apply's order).
+enum { CG3_A = 0, CG3_B = 1, CG3_S = 2 };
+
+struct SW3Row {    // raw loads for one step: centre row (with the strip-border
+                   // point) and the two side rows, of one or two vectors
+    double ac, ae, am, ap, bc, be, bm, bp, xo, ro;
+};
+
+template <int MODE>
+__device__ __forceinline__ void sw3_issue(const double *__restrict__ va, const double *__restrict__ vb,
+                                          const double *__restrict__ x, const double *__restrict__ r, int n, int z,
+                                          int k, int ya, int yb, int xcol, bool lv, int eoff, bool eok,
+                                          bool use_b, SW3Row &w) {
+    const long long plane = (long long)n * n;
+    const bool kok = k >= 0 && k < n;
+    const int y = k - 1;                        // output row of this step
+    const bool yok = y >= ya && y < yb;
+    const long long base = ((long long)z * n + (kok ? k : 0)) * n + xcol;
+    const long long ob = ((long long)z * n + (yok ? y : 0)) * n + xcol;
+    const long long ic = (kok && lv) ? base : 0;
+    const long long ie = (kok && eok) ? base + eoff : 0;
+    const long long im = (yok && lv && z > 0) ? ob - plane : 0;
+    const long long ip = (yok && lv && z + 1 < n) ? ob + plane : 0;
+    w.ac = va[ic];
+    w.ae = va[ie];
+    w.am = va[im];
+    w.ap = va[ip];
+    if (use_b) {
+        w.bc = vb[ic];
+        w.be = vb[ie];
+        w.bm = vb[im];
+        w.bp = vb[ip];
+    }
+    if constexpr (MODE == CG3_B) {
+        const long long io = (yok && lv) ? ob : 0;
+        w.xo = x[io];
+        w.ro = r[io];
+    }
+}
+
+template <int MODE, int PF>
+__device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, double s, double coef,
+                                             bool first, const double *__restrict__ va,
+                                             const double *__restrict__ vb, double *__restrict__ x,
+                                             double *__restrict__ r, double *__restrict__ pout, double &acc0,
+                                             double &acc1) {
+    const int n = g.n;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const bool l0 = lane == 0, l63 = lane == WAVE - 1;
+    const int waves = size * nwaves();
+    const int wid = rank * nwaves() + wave_id();
+    const bool use_b = MODE == CG3_A && !first;
+    // y-segments: about one (strip, plane, segment) unit per wave, at least 16 rows
+    const long long rows = (long long)n * n * g.cpr;
+    const int per = (int)min((long long)n, (rows + waves - 1) / waves);
+    const int seg = max(min(16, n), per);
+    const int nseg = (n + seg - 1) / seg;
+    const long long units = (long long)g.cpr * n * nseg;
+    for (long long u = wid; u < units; u += waves) {
+        const int sx = (int)(u % g.cpr);
+        const long long rem = u / g.cpr;
+        const int z = (int)(rem % n);
+        const int ya = (int)(rem / n) * seg;
+        const int yb = min(n, ya + seg);
+        const int xcol = sx * WAVE + lane;
+        const bool lv = xcol < n;
+        const bool eok = (l0 && xcol > 0) || (l63 && xcol + 1 < n);
+        const int eoff = l0 ? -1 : 1;
+        const bool zmok = z > 0, zpok = z + 1 < n;
+        const int nrows = yb - ya + 2;   // centre rows ya-1 .. yb
+        double vm2 = 0.0, vm1c = 0.0, vm1l = 0.0, vm1r = 0.0;   // v at rows k-2 (centre) and k-1
+        SW3Row ring[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+            if (q < nrows)
+                sw3_issue<MODE>(va, vb, x, r, n, z, ya - 1 + q, ya, yb, xcol, lv, eoff, eok, use_b, ring[q]);
+        for (int tb = 0; tb < nrows; tb += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int t = tb + q;
+                if (t >= nrows) break;
+                const int k = ya - 1 + t;
+                const SW3Row w = ring[q];
+                if (t + PF < nrows)
+                    sw3_issue<MODE>(va, vb, x, r, n, z, k + PF, ya, yb, xcol, lv, eoff, eok, use_b, ring[q]);
+                const bool kok = k >= 0 && k < n;
+                const int y = k - 1;
+                const bool yok = y >= ya && y < yb;
+                // v at row k (centre, strip-border point) and at row y in the planes z -/+ 1
+                double vc = (kok && lv) ? w.ac : 0.0;
+                double ve = (kok && eok) ? w.ae : 0.0;
+                double vmz = (yok && lv && zmok) ? w.am : 0.0;
+                double vpz = (yok && lv && zpok) ? w.ap : 0.0;
+                if (use_b) {
+                    vc = __builtin_fma(coef, (kok && lv) ? w.bc : 0.0, vc);
+                    ve = __builtin_fma(coef, (kok && eok) ? w.be : 0.0, ve);
+                    vmz = __builtin_fma(coef, (yok && lv && zmok) ? w.bm : 0.0, vmz);
+                    vpz = __builtin_fma(coef, (yok && lv && zpok) ? w.bp : 0.0, vpz);
+                }
+                // lane shifts on every lane, then the strip-border lanes
+                const double sl = from_lower_lane(vc), sr = from_upper_lane(vc);
+                const double vl = l0 ? ve : sl;
+                const double vr = l63 ? ve : sr;
+                if (yok) {
+                    // A v at (x, y, z): ((up + down) + (front + back)) + (left + right)
+                    const double s2 = (vm2 + vc) + (vmz + vpz);
+                    const double av = be_point(vm1c, s2 + (vm1l + vm1r), 6.0, s);
+                    if (lv) {
+                        const long long i = ((long long)z * n + y) * n + xcol;
+                        if constexpr (MODE == CG3_A) {
+                            pout[i] = vm1c;
+                            acc0 = __builtin_fma(vm1c, av, acc0);
+                        } else if constexpr (MODE == CG3_B) {
+                            x[i] = __builtin_fma(coef, vm1c, w.xo);
+                            const double rv = __builtin_fma(-coef, av, w.ro);
+                            r[i] = rv;
+                            acc0 = __builtin_fma(rv, rv, acc0);
+                        } else {
+                            const double rv = vm1c - av;
+                            x[i] = vm1c;
+                            r[i] = rv;
+                            acc0 = __builtin_fma(rv, rv, acc0);
+                            acc1 = __builtin_fma(vm1c, vm1c, acc1);
+                        }
+                    }
+                }
+                vm2 = vm1c;
+                vm1c = vc;
+                vm1l = vl;
+                vm1r = vr;
+            }
+        }
+    }
+}
+
 // Solves (I - s h^2 L_h) x = b by CG with the team (DIM = 2 or 3; U chunks
 // per wave and loop trip, whose loads are all issued before the first is
 // used: memory-level parallelism against register use).  Returns
@@ -285,10 +430,12 @@ __device__ __forceinline__ double cpt_apply(const CPt &q, const double (&v)[2 * 
 // neighbours from r and p_old), stores p and reduces <p, A p>; phase B
 // updates x and r, recomputing A p from the stored p (bit-identical to phase
 // A's value) instead of storing it: 64 B of HBM traffic per point.
-template <int DIM, int U>
+// SW3 (DIM = 3): the phases march (cg3_sweep_sw) instead of visiting chunks.
+template <int DIM, int U, bool SW3 = false>
 __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int maxit,
                            const double *__restrict__ b, double *__restrict__ x, const CGWork &wk,
                            double abs_thresh2) {
+    static_assert(!SW3 || DIM == 3, "the marching phases are three-dimensional");
     constexpr int V = 2 * DIM;
     __shared__ double lds[MAX_WAVES];
     const double twod = 2.0 * DIM;
@@ -299,7 +446,10 @@ __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int ma
     double *__restrict__ r = wk.r;
     const bool from_zero = abs_thresh2 >= 0.0;
 
-    double rr_p = 0.0, bb_p = 0.0;
+    double rr_p = 0.0, bb_p = 0.0, unused = 0.0;
+    if (SW3 && !from_zero)
+        cg3_sweep_sw<CG3_S, 4>(g, tm.rank, tm.size, s, 0.0, true, b, nullptr, x, r, nullptr, rr_p, bb_p);
+    else
     for (long long c0 = cr.begin + w; c0 < cr.end; c0 += U * nw) {
         CPt q[U];
         bool act[U];
@@ -356,6 +506,10 @@ __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int ma
     while (it < maxit && rr > thresh) {
         // phase A: p = r + beta p_old (also at the neighbours), <p, A p>
         double pq_p = 0.0;
+        if (SW3)
+            cg3_sweep_sw<CG3_A, 4>(g, tm.rank, tm.size, s, beta, it == 0, r, pold, nullptr, nullptr, pcur, pq_p,
+                                   unused);
+        else
         for (long long c0 = cr.begin + w; c0 < cr.end; c0 += U * nw) {
             CPt q[U];
             bool act[U];
@@ -382,6 +536,10 @@ __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int ma
         const double alpha = rr / pq;
         // phase B: x += alpha p, r -= alpha A p, <r, r>
         double rn_p = 0.0;
+        if (SW3)
+            cg3_sweep_sw<CG3_B, 4>(g, tm.rank, tm.size, s, alpha, false, pcur, nullptr, x, r, nullptr, rn_p,
+                                   unused);
+        else
         for (long long c0 = cr.begin + w; c0 < cr.end; c0 += U * nw) {
             CPt q[U];
             bool act[U];

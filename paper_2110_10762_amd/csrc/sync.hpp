@@ -118,10 +118,11 @@ struct SweepBufs {
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWork &wk, double abs_thresh2) {
-    // 3D whole-GPU sweep: two chunks in flight per wave (8.7 s for the 3D
-    // workload against 9.0 s with one; the one-synchronisation form with w
-    // and s stored moves 80 B per point and took 10.9 s)
-    return cg_team_dim<DIM, 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+    // 3D whole-GPU sweep: marching phases (7.7 s for the 3D workload against
+    // 8.7 s with two chunks per wave in flight and 9.0 s with one; the
+    // one-synchronisation form with w and s stored moves 80 B per point and
+    // took 10.9 s)
+    return cg_team_dim<DIM, 2, DIM == 3>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
 
 template <int DIM>
