@@ -164,6 +164,16 @@ def test_free_mode_2d_small_and_ragged_grids(n):
     assert rel(lam, star) <= TOL
 
 
+def test_free_mode_3d_ragged():
+    # n = 70: the marching CG phases of the async teams cross an x-strip border
+    p = workloads.heat3d(n=70, nslices=3, T=2e-3)
+    d = disc_of(p)
+    prob, lam, st = solve(p, pr.PR_ASYNC_FREE)
+    assert st.converged == 1
+    star = heat.serial_fine(p.u0, d.r, d.m, d.nslices)
+    assert rel(lam, star) <= TOL
+
+
 def test_free_mode_with_injected_delays_1d():
     p = workloads.heat1d()
     d = disc_of(p)

@@ -190,7 +190,9 @@ def test_sync_finite_termination_bitwise_gpu():
         assert rel(lam, heat.serial_fine(p.u0, d.r, d.m, d.nslices)) <= 1e-12
 
 
-@pytest.mark.parametrize("n,N,T", [(31, 8, 2e-2), (70, 6, 5e-3)])
+# n = 70 and 130: two and three column strips of the coarse solver, the last
+# one ragged
+@pytest.mark.parametrize("n,N,T", [(31, 8, 2e-2), (70, 6, 5e-3), (130, 5, 5e-3)])
 def test_sync_2d_vs_oracle(n, N, T):
     p = workloads.heat2d(n=n, nslices=N, T=T)
     d = disc_of(p)
@@ -208,6 +210,17 @@ def test_sync_3d_small_vs_oracle():
     _, lam, st = run_sync(p, eps=0.0, kmax=3)
     props = heat.Propagators(d, cg_tol=p.cg_tol)
     ref = parareal.parareal_sync(p.u0, props.F, props.G, d.nslices, eps=0.0, kmax=3)
+    assert rel(lam, ref.lam) <= TOL
+
+
+def test_sync_3d_ragged_vs_oracle():
+    # n = 70: two x-strips per row (the marching CG phases cross a strip
+    # border), the second one ragged
+    p = workloads.heat3d(n=70, nslices=3, T=2e-3)
+    d = disc_of(p)
+    _, lam, st = run_sync(p, eps=0.0, kmax=2)
+    props = heat.Propagators(d, cg_tol=p.cg_tol)
+    ref = parareal.parareal_sync(p.u0, props.F, props.G, d.nslices, eps=0.0, kmax=2)
     assert rel(lam, ref.lam) <= TOL
 
 
