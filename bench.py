@@ -86,9 +86,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU; the method's slices would shard "
-              "over GPUs by contiguous blocks (see the design notes), but no multi-GPU "
-              "path is built or timed", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; the method's slices would shard "
+              "over GPUs by contiguous blocks, but no multi-GPU path is built or timed",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

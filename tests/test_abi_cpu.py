@@ -17,7 +17,7 @@ def declared_symbols():
     return sorted(set(re.findall(r"\b(pr_[a-z_]+)\s*\(", text)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_solver_calls():
     syms = declared_symbols()
     for s in ("pr_create", "pr_solve_sync", "pr_solve_async", "pr_grad", "pr_destroy"):
         assert s in syms
