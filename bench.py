@@ -202,7 +202,7 @@ def main():
             # per update: F passes, predecessor copy 16, correction + next slot 48
             a_bytes += (upd * (a_passes * 16.0 + 16.0 + 48.0) + x["kernel_cg_iters"] * 48.0
                         + solves * 24.0) * npts
-        rl["async"] = {"kernel": f"k_async<2,2,128,{ASYNC_DEPTH}>", "bound": "hbm",
+        rl["async"] = {"kernel": f"k_async<2,2,64,{ASYNC_DEPTH}>", "bound": "hbm",
                        "achieved": a_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "launches": len(a), "avg_launch_ms": k_ms / len(a)}
     same_sources = sources_digest() == PROFILED_SOURCES

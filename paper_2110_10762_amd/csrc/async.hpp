@@ -289,15 +289,11 @@ __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const do
                 const int st = min(D, a.m - p * D);
                 const int total = a.nsx * a.nsy;
                 for (int sidx = wid; sidx < total; sidx += waves) {
-                    if constexpr (RR >= SW_MIN_ROWS) {
-                        const int ya = (sidx % a.nsy) * RR;
-                        // two rows in flight: this persistent kernel's occupancy is set by
-                        // its registers, and CG, not F, dominates its time
-                        fine2d_sw<XP, D, 2, false>(cur, tgt, a.n, a.r, st, sidx / a.nsy, ya, min(a.n, ya + RR),
-                                         (sidx % a.nsy) & 1);
-                    } else {
-                        fine2d_strip<XP, RR, D>(cur, tgt, a.n, a.r, st, sidx / a.nsy, sidx % a.nsy);
-                    }
+                    const int ya = (sidx % a.nsy) * RR;   // sliding window over RR rows
+                    // two rows in flight: this persistent kernel's occupancy is set by
+                    // its registers, and CG, not F, dominates its time
+                    fine2d_sw<XP, D, 2, false>(cur, tgt, a.n, a.r, st, sidx / a.nsy, ya, min(a.n, ya + RR),
+                                               (sidx % a.nsy) & 1);
                 }
             } else {
                 const int total = a.nsx * a.nsy * a.nsz;
