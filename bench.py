@@ -28,10 +28,10 @@ ASYNC_DEPTH = 8         # fine steps per pass inside the persistent asynchronous
 # --pmc runs (FETCH_SIZE scaled by 1.993, WRITE_SIZE by 1.000: the factors a
 # plain copy of known size gives), kept in profiles/.  They describe the
 # kernel sources with this digest and are reported as null once those change.
-PROFILED_SOURCES = "b8255d9f0e0a8bfb"
-PROFILED_TRAFFIC = {"async": 1842.36 + 1762.74,      # GB, one launch
-                    "fine": 0.5198 + 0.4911,          # GB, mean over the sync solve's passes
-                    "sweep": 87.1600 + 85.2865}       # GB, mean over the sync solve's sweeps
+PROFILED_SOURCES = "bc01517090fc98ce"
+PROFILED_TRAFFIC = {"async": 1866.11 + 1787.88,      # GB, one launch
+                    "fine": 0.5200 + 0.4911,          # GB, mean over the sync solve's passes
+                    "sweep": 87.1653 + 85.2865}       # GB, mean over the sync solve's sweeps
 
 
 def sources_digest():
