@@ -28,10 +28,10 @@ ASYNC_DEPTH = 8         # fine steps per pass inside the persistent asynchronous
 # --pmc runs (FETCH_SIZE scaled by 1.993, WRITE_SIZE by 1.000: the factors a
 # plain copy of known size gives), kept in profiles/.  They describe the
 # kernel sources with this digest and are reported as null once those change.
-PROFILED_SOURCES = "bc01517090fc98ce"
-PROFILED_TRAFFIC = {"async": 1866.11 + 1787.88,      # GB, one launch
-                    "fine": 0.5200 + 0.4911,          # GB, mean over the sync solve's passes
-                    "sweep": 87.1653 + 85.2865}       # GB, mean over the sync solve's sweeps
+PROFILED_SOURCES = "b26b5e49d309486d"
+PROFILED_TRAFFIC = {"async": 1639.66 + 1526.30,      # GB, one launch
+                    "fine": 0.5202 + 0.4911,          # GB, mean over the sync solve's passes
+                    "sweep": 87.1668 + 85.2865}       # GB, mean over the sync solve's sweeps
 
 
 def sources_digest():

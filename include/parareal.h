@@ -145,9 +145,10 @@ typedef struct pr_stats {
 
 typedef struct pr_async_opts {
     int mode;                /* PR_ASYNC_* */
-    int teams;               /* concurrent slice teams, each taking its slices round-robin;
+    int teams;               /* concurrent slice teams, each holding the slices that
+                                slice_blocks assigns it and updating them in turn;
                                 0 = automatic: one per slice in 1D and in REPLAY (which
-                                needs it), else one per XCD (8 on MI355X) */
+                                needs it), else four, each spanning two XCDs */
     int max_local_iters;     /* cap on k_i (<= 0: 4*N + 16) */
     const int *schedule;     /* REPLAY: host array [N][max_local_iters]: predecessor
                                 version read by slice i's k-th coarse solve (slice 1: 0) */
