@@ -125,6 +125,7 @@ struct AsyncArgs {
     unsigned long long *counters;   // cg iterations, coarse solves, skipped solves, copy retries, idle rounds
     // fine-kernel geometry
     int nsx, nsy, nsz, zc;
+    int rows;                // 2D: rows of a fine sliding-window segment
     const double *inv_tab;   // 1D Thomas factors
     unsigned long long t_limit;  // wall-clock ticks before the launch gives up
 };
@@ -289,10 +290,10 @@ __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const do
                 const int st = min(D, a.m - p * D);
                 const int total = a.nsx * a.nsy;
                 for (int sidx = wid; sidx < total; sidx += waves) {
-                    const int ya = (sidx % a.nsy) * RR;   // sliding window over RR rows
+                    const int ya = (sidx % a.nsy) * a.rows;   // sliding window over a.rows rows
                     // two rows in flight: this persistent kernel's occupancy is set by
                     // its registers, and CG, not F, dominates its time
-                    fine2d_sw<XP, D, 2, false>(cur, tgt, a.n, a.r, st, sidx / a.nsy, ya, min(a.n, ya + RR),
+                    fine2d_sw<XP, D, 2, false>(cur, tgt, a.n, a.r, st, sidx / a.nsy, ya, min(a.n, ya + a.rows),
                                                (sidx % a.nsy) & 1);
                 }
             } else {
@@ -358,7 +359,9 @@ enum { ACT_IDLE = 0, ACT_UPDATE = 1, ACT_DONE = 2 };
 
 // The arguments live in device memory: read through a uniform pointer they
 // stay in scalar registers, where a by-value struct passed on by reference
-// would be copied to scratch.
+// would be copied to scratch.  XP: x points per lane of F; RR: points per
+// lane in 1D, rows per strip in 3D (2D takes its fine segment length at run
+// time, RR = 0); D: fine steps per pass.
 template <int DIM, int XP, int RR, int D, bool IMPL = false>
 // Two workgroups per CU in 2D and 3D: 256 registers per lane, room for the
 // two chunks in flight of the 2D coarse solver without spills.
