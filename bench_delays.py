@@ -3,8 +3,9 @@ against asynchronous Parareal (Algorithm 2) under emulated message latency,
 on the 2D heat workload (1024^2 interior points, 64 slices, nu = 1, T = 1e-3,
 fine dt = 0.2 h^2, backward-Euler coarse step by CG to 1e-12, stop at 1e-10).
 
-Two team layouts: one team per slice (the paper's p = N processors), and one
-team per XCD holding a contiguous block of slices.  A published slice value
+Three team layouts: one team per slice (the paper's p = N processors), one
+team per XCD, and the library's default of four teams of two XCDs, each of
+the last two holding a contiguous block of slices.  A published slice value
 becomes readable by the successor only `latency` after its publication, the
 emulated transfer of Section 4.1.  For every latency both drivers run to the
 tolerance; the lines report wall time, k, kappa, the per-team costs C_F and
@@ -32,7 +33,7 @@ sys.path.insert(0, ROOT)
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--latency-ms", default="0,3,10,30,100")
-    ap.add_argument("--teams", default="64,8", help="team counts (64: one per slice)")
+    ap.add_argument("--teams", default="64,8,4", help="team counts (64: one per slice)")
     ap.add_argument("--gpus", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
