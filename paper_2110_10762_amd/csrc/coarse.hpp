@@ -430,7 +430,8 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
 // neighbours from r and p_old), stores p and reduces <p, A p>; phase B
 // updates x and r, recomputing A p from the stored p (bit-identical to phase
 // A's value) instead of storing it: 64 B of HBM traffic per point.
-// SW3 (DIM = 3): the phases march (cg3_sweep_sw) instead of visiting chunks.
+// SW3 (DIM = 3): the two phases and the set-up from x0 = b march
+// (cg3_sweep_sw) instead of visiting chunks.
 template <int DIM, int U, bool SW3 = false>
 __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int maxit,
                            const double *__restrict__ b, double *__restrict__ x, const CGWork &wk,
