@@ -58,3 +58,31 @@ def test_create_without_gpu_fails_cleanly():
     rc = lib.pr_create(ctypes.byref(cfg), 1, 0, None, ctypes.byref(h))
     assert rc != 0 and not h.value
     assert lib.pr_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for script in ("bench.py", "bench_delays.py"):
+        res = subprocess.run([sys.executable, os.path.join(root, script), "--gpus", "2"],
+                             capture_output=True, text=True, timeout=120)
+        assert res.returncode == 2, (script, res.stderr)
+        assert "one GPU" in res.stderr, (script, res.stderr)
+
+
+def test_bench_source_digest_ignores_comments(tmp_path, monkeypatch):
+    import importlib
+    import shutil
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    bench = importlib.import_module("bench")
+    src = os.path.join(root, "paper_2110_10762_amd", "csrc")
+    fake = tmp_path / "paper_2110_10762_amd" / "csrc"
+    shutil.copytree(src, fake)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    d0 = bench.sources_digest()
+    p = fake / "common.hpp"
+    p.write_text(p.read_text() + "\n// a comment\n/* another\n one */\n")
+    assert bench.sources_digest() == d0
+    p.write_text(p.read_text() + "\nstatic int pr_digest_probe_ = 1;\n")
+    assert bench.sources_digest() != d0
