@@ -30,9 +30,9 @@ ASYNC_DEPTH = 8         # fine steps per pass inside the persistent asynchronous
 # kernel sources whose code (comments aside) has this digest and are reported
 # as null once that code changes.
 PROFILED_SOURCES = "aa308ccc010bd6f9"
-PROFILED_TRAFFIC = {"async": 1589.95 + 1470.82,      # GB, one launch
-                    "fine": 0.5200 + 0.4911,          # GB, mean over the sync solve's passes
-                    "sweep": 86.9228 + 85.2865}       # GB, mean over the sync solve's sweeps
+PROFILED_TRAFFIC = {"async": 1609.74 + 1488.77,      # GB, one launch
+                    "fine": 0.5202 + 0.4911,          # GB, mean over the sync solve's passes
+                    "sweep": 87.1866 + 85.2865}       # GB, mean over the sync solve's sweeps
 
 
 def sources_digest():
@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--cpu-sample-slices", type=int, default=96)
     ap.add_argument("--only", choices=["both", "sync", "async"], default="both",
                     help="restrict the step to one driver (profiling runs)")
+    ap.add_argument("--no-pipelined", action="store_true",
+                    help="skip the untimed pipelined synchronous solve (Algorithm 1)")
     ap.add_argument("--no-increment", action="store_true",
                     help="skip the untimed runs with coarse solves on input changes")
     return ap.parse_args()
@@ -164,6 +166,19 @@ def main():
             incr[drv] = {"ms": st.wall_ms, "iters": st.iters, "cg_iters": st.cg_iters,
                          "rel_err_vs_serial_fine": (lam_i - ser).abs().max().item() / ser.abs().max().item()}
 
+    # the pipelined synchronous driver (Algorithm 1, per-slice waits, the
+    # default async teams), also outside the timed region
+    pipe = None
+    if not args.no_pipelined and args.only == "both":
+        prob.set_async_options(mode=pr.PR_ASYNC_PIPELINED, time_limit_s=200.0)
+        lam_p = torch.empty_like(lam_s)
+        st = pr.Stats(N)
+        prob.solve_async(u0, lam_p, st)
+        pipe = {"ms": st.wall_ms, "iters": st.iters,
+                "rel_err_vs_serial_fine": (lam_p - ser).abs().max().item() / ser.abs().max().item()}
+        prob.set_async_options(mode=pr.PR_ASYNC_FREE, time_limit_s=200.0)
+        del lam_p
+
     sref = ser.abs().max().item()
     err_s = (lam_s - ser).abs().max().item() / sref if rec["sync"] else None
     err_a = (lam_a - ser).abs().max().item() / sref if rec["async"] else None
@@ -240,6 +255,7 @@ def main():
         "roofline_fine": rl.get("fine"),
         "fine_sweep": fine_sweep,
         "time_to_tol_ms_increment": incr,
+        "time_to_tol_ms_pipelined_sync": pipe,
         "roofline_kernels": rl,
         "time_to_tol_ms": {
             "sync": float(np.median([x["wall_ms"] for x in rec["sync"]])) if rec["sync"] else None,
