@@ -56,11 +56,3 @@ def grad_reverse(u0: np.ndarray, target: np.ndarray, r: float, M: int,
         mu = heat.fine_step(mu, r)                  # A^T mu (A symmetric)
     return mu, dldnu
 
-
-def grad_upstream(u0: np.ndarray, gT: np.ndarray, r: float, M: int, dt: float,
-                  h: float):
-    """Vector-Jacobian product for an arbitrary upstream gradient gT = dL/du(T)."""
-    u_prev = heat.fine(u0, r, M - 1)
-    dldu0 = heat.fine(gT, r, M)
-    lap = heat.laplacian_h2(u_prev) / (h * h)
-    return dldu0, M * dt * float(np.vdot(gT, lap))

@@ -206,6 +206,67 @@ def test_coarse_on_sine_mode():
     assert np.max(np.abs(got - u / (1 + s * mu))) <= 1e-11
 
 
+@pytest.mark.parametrize("dim,n,N", [(1, 31, 6), (2, 15, 5), (3, 7, 4)])
+def test_spectral_serial_fine_vs_stencil_all_slices(dim, n, N):
+    # the modal serial fine run against the stencil one (itself pinned to the
+    # sine-mode amplification and to dense matrix powers), every slice
+    rng = np.random.default_rng(40 + dim)
+    u0 = rng.standard_normal((n,) * dim)
+    r, m = 0.8 / (2 * dim), 11
+    want = heat.serial_fine(u0, r, m, N)
+    got = spectral.serial_fine(u0, r, m, N)
+    assert got.shape == want.shape
+    for i in range(N + 1):
+        assert np.max(np.abs(got[i] - want[i])) <= 1e-13 * max(1.0, np.max(np.abs(want[i]))), i
+    sub = spectral.serial_fine(u0, r, m, N, slices=[N, 0, 2])
+    assert np.max(np.abs(sub - want[[N, 0, 2]])) <= 1e-13 * np.max(np.abs(want))
+
+
+def test_spectral_serial_fine_heat1d_closed_form_every_slice():
+    # lambda*_i of the 1D workload written out mode by mode:
+    # sum_k a_k (1 - 4 r sin^2(k pi h / 2))^(i m) sin(k pi x)
+    p = workloads.heat1d()
+    d = _disc(p)
+    x = workloads.grid(p.n)
+    got = spectral.serial_fine(p.u0, d.r, d.m, d.nslices)
+    for i in range(d.nslices + 1):
+        want = np.zeros(p.n)
+        for k, a in enumerate(p.amps, start=1):
+            want += a * (1 - 4 * d.r * math.sin(k * math.pi * d.h / 2) ** 2) ** (i * d.m) * np.sin(k * np.pi * x)
+        assert np.max(np.abs(got[i] - want)) <= 1e-13 * np.max(np.abs(want)), i
+
+
+def test_spectral_serial_fine_anisotropic_mode():
+    # a 2D mode with different wave numbers along the two axes: each slice
+    # multiplies it by (1 - r (mu_kx + mu_ky))^m
+    n, r, m, N = 40, 0.2, 13, 7
+    h = 1.0 / (n + 1)
+    x = np.arange(1, n + 1) * h
+    u0 = np.outer(np.sin(3 * np.pi * x), np.sin(11 * np.pi * x))
+    mu = 4 * math.sin(3 * math.pi * h / 2) ** 2 + 4 * math.sin(11 * math.pi * h / 2) ** 2
+    got = spectral.serial_fine(u0, r, m, N)
+    for i in range(N + 1):
+        assert np.max(np.abs(got[i] - (1 - r * mu) ** (i * m) * u0)) <= 1e-13, i
+
+
+def test_spectral_parareal_sync_endpoints():
+    # k = 0 is the coarse sweep g^i u0 (dense solves); k >= i is the serial
+    # fine value (finite termination)
+    rng = np.random.default_rng(12)
+    n, r, m, s, N = 6, 0.2, 9, 1.7, 5
+    u0 = rng.standard_normal((n, n))
+    Mg = heat.be_matrix(2, n, s)
+    lam = u0.ravel()
+    k0 = spectral.parareal_sync(u0, r, m, s, 0, range(N + 1))
+    for i in range(N + 1):
+        assert np.max(np.abs(k0[i].ravel() - lam)) <= 1e-12 * np.max(np.abs(lam)), i
+        lam = np.linalg.solve(Mg, lam)
+    ser = heat.serial_fine(u0, r, m, N)
+    for i in range(N + 1):
+        got = spectral.parareal_sync(u0, r, m, s, i, [i])[0]
+        assert np.max(np.abs(got - ser[i])) <= 1e-12 * np.max(np.abs(ser[i])), i
+
+
 def test_spectral_propagators_vs_dense():
     rng = np.random.default_rng(5)
     u = rng.standard_normal((7, 7))
@@ -382,7 +443,72 @@ def test_async_random_schedules_converge_and_terminate(seed, delay):
     assert st.kappa >= sync.iters                     # kappa(k~) >= k (Section 4.2)
     st2 = parareal.run_random(p.u0, pr.F, pr.G, d.nslices, seed=seed, max_delay=delay, eps=p.eps)
     assert st2.converged_tol(p.eps)
-    assert np.max(np.abs(st2.current() - star)) < 1e-8
+    assert np.max(np.abs(st2.current() - star)) < 1e-10 * np.max(np.abs(star))
+
+
+def _stale_tail_state(K):
+    # 1D workload after K synchronous sweeps; slice N then re-reads the
+    # predecessor version it already used until its own change is 0 (stale
+    # input gives F exactly), and slices 1..N-1 make two more sweeps reading
+    # their newest predecessor while slice N does not update
+    p = workloads.heat1d()
+    d = _disc(p)
+    pr = heat.Propagators(d)
+    N = d.nslices
+    st = parareal.replay(p.u0, pr.F, pr.G, N, parareal.sync_schedule(N, K))
+    st.step(N, st.f_ver[N])
+    st.step(N, st.f_ver[N])
+    for _ in range(2):
+        for i in range(1, N):
+            st.step(i, st.newest(i - 1))
+    return st, N
+
+
+def test_async_tolerance_stop_rejects_a_stale_predecessor():
+    # every slice's last change is below eps, but the predecessor slice N last
+    # read has moved by more than eps since: the tolerance stop must refuse
+    st, N = _stale_tail_state(8)
+    last = max(st.delta[1:])
+    actual = float(np.max(np.abs(st.versions[N - 1][-1] - st.versions[N - 1][st.g_ver[N]])))
+    eps = 2.5e-7
+    assert st.delta[N] == 0.0 and last < eps <= actual
+    assert min(st.k[1:]) > 0
+    assert not st.converged_tol(eps)
+    # the same state passes once eps exceeds the recorded drift of every input
+    assert st.staleness(N) < 1e-6 and st.converged_tol(1e-6)
+
+
+def test_async_tolerance_stop_accepts_small_drift_only():
+    st, N = _stale_tail_state(10)
+    assert max(st.delta[1:]) < 1e-8
+    drift = st.staleness(N)
+    assert 3e-8 < drift < 1e-7
+    assert st.converged_tol(1e-7)
+    assert not st.converged_tol(3e-8)      # all changes < 3e-8, drift is not
+    # a slice that never updated blocks the stop whatever its recorded change
+    fresh = parareal.AsyncReplay(np.ones(3), lambda x: x, lambda x: x, 2)
+    fresh.step(1, 0)
+    assert fresh.delta[2] == np.inf and not fresh.converged_tol(1.0)
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_async_drift_bounds_the_true_staleness(seed):
+    # the recorded changes bound, by the triangle inequality, how far the
+    # newest predecessor is from the one a slice last read
+    p = workloads.heat2d(n=9, nslices=5, T=2e-2)
+    d = _disc(p)
+    pr = heat.Propagators(d, cg_tol=1e-13)
+    rng = np.random.default_rng(seed)
+    st = parareal.AsyncReplay(p.u0, pr.F, pr.G, d.nslices)
+    for _ in range(80):
+        i = int(rng.integers(1, d.nslices + 1))
+        hi = st.newest(i - 1)
+        st.step(i, int(rng.integers(max(st.f_ver[i], hi - 3), hi + 1)))
+        for s in range(2, d.nslices + 1):
+            if st.g_ver[s] < 0:
+                continue
+            true = float(np.max(np.abs(st.versions[s - 1][-1] - st.versions[s - 1][st.g_ver[s]])))
+            assert true <= st.staleness(s) * (1 + 1e-12) + 1e-300
 
 
 def test_async_contraction_when_alpha_below_one():
