@@ -22,14 +22,19 @@ orthonormal) is a library routine that moves between grid and mode values.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 import scipy.fft
 
 
+_WORKERS = max(1, min(16, os.cpu_count() or 1))
+
+
 def dst(u: np.ndarray) -> np.ndarray:
-    """Orthonormal DST-I over every axis (its own inverse)."""
-    return scipy.fft.dstn(u, type=1, norm="ortho")
+    """Orthonormal DST-I over every axis (its own inverse); the library
+    routine's own threads share the 1D transforms of large grids."""
+    return scipy.fft.dstn(u, type=1, norm="ortho", workers=_WORKERS)
 
 
 idst = dst
@@ -90,3 +95,22 @@ def parareal_sync(u0: np.ndarray, r: float, m: int, s: float, k: int,
     f, g = symbols(u0.ndim, u0.shape[0], r, m, s)
     u0h = dst(u0)
     return np.stack([idst(parareal_coefficients(f, g, i, k) * u0h) for i in slices])
+
+
+def parareal_sync_change(u0: np.ndarray, r: float, m: int, s: float, k: int,
+                         slices) -> np.ndarray:
+    """lambda_i^k - lambda_i^{k-1} of synchronous Parareal with exact G for the
+    requested slices: by the closed form above only the j = k term changes,
+    C(i, k) (f - g)^k g^(i-k) per mode (zero for slices i < k, which are
+    already exact).  Its max norm over all slices is the change of the
+    stopping test, eq. (thresh)."""
+    f, g = symbols(u0.ndim, u0.shape[0], r, m, s)
+    u0h = dst(u0)
+    d = f - g
+    out = []
+    for i in slices:
+        if i < k or k < 1:
+            out.append(np.zeros_like(u0))
+        else:
+            out.append(idst(float(math.comb(i, k)) * d ** k * g ** (i - k) * u0h))
+    return np.stack(out)

@@ -7,8 +7,11 @@ the compiled library is missing -- there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from typing import Optional, Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -139,8 +142,13 @@ def _check(rc: int, allow=()):
     return rc
 
 
-def _ptr(x) -> int:
-    """Device pointer of a torch tensor (float64, contiguous, on a GPU) or an int."""
+def _ptr(x, numel: Optional[int] = None, at_least: bool = False) -> int:
+    """Device pointer of a torch tensor (float64, contiguous, on a GPU) or an int.
+
+    numel: the element count the library will read or write through the
+    pointer; a tensor of another size (fewer elements, with at_least) is
+    refused before any kernel sees it.  Raw integer pointers are the caller's
+    responsibility."""
     if x is None:
         return 0
     if isinstance(x, int):
@@ -152,6 +160,11 @@ def _ptr(x) -> int:
         raise ValueError("buffers must live in GPU memory")
     if x.dtype != torch.float64 or not x.is_contiguous():
         raise ValueError("buffers must be contiguous float64")
+    if numel is not None:
+        bad = x.numel() < numel if at_least else x.numel() != numel
+        if bad:
+            raise ValueError(f"buffer holds {x.numel()} values, the call needs "
+                             f"{'at least ' if at_least else ''}{numel}")
     return x.data_ptr()
 
 
@@ -206,6 +219,20 @@ class Stats:
         return d
 
 
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Destroys every handle still open while the interpreter can still make
+    HIP calls (before profilers and the runtime tear down)."""
+    for p in list(_live):
+        try:
+            p.close()
+        except Exception:
+            pass
+
+
 class Problem:
     """Owns one library handle (one problem, or a batch when given several configs)."""
 
@@ -223,13 +250,28 @@ class Problem:
         self.lib = lib
         self.nproblems = len(cfgs)
         self.cfgs = list(cfgs)
+        self.npts = [c.n ** c.dim for c in self.cfgs]
+        self.state_numel = sum(self.npts)
+        self.iterate_numel = sum((c.nslices + 1) * q for c, q in zip(self.cfgs, self.npts))
+        _live.add(self)
 
     def close(self):
+        """Waits for the handle's work and frees it (idempotent)."""
         if getattr(self, "h", None) and self.h.value:
             self.lib.pr_destroy(self.h)
             self.h = ctypes.c_void_p()
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        # no HIP call once the interpreter is shutting down: the runtime (and
+        # any profiler attached to it) may already be gone
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -242,7 +284,8 @@ class Problem:
 
     def _solve(self, fn, u0, lam, stats: Optional[Stats], allow=()):
         st = stats.raw if stats is not None else None
-        return _check(fn(self.h, _ptr(u0), _ptr(lam), ctypes.byref(st) if st is not None else None), allow)
+        return _check(fn(self.h, _ptr(u0, self.state_numel), _ptr(lam, self.iterate_numel),
+                         ctypes.byref(st) if st is not None else None), allow)
 
     def solve_sync(self, u0, lam, stats: Optional[Stats] = None, allow_notconv=False):
         return self._solve(self.lib.pr_solve_sync, u0, lam, stats, (PR_ENOTCONV,) if allow_notconv else ())
@@ -275,15 +318,18 @@ class Problem:
 
     def grad(self, lam, gT, dldu0) -> float:
         out = ctypes.c_double()
-        _check(self.lib.pr_grad(self.h, _ptr(lam), _ptr(gT), _ptr(dldu0), ctypes.byref(out)))
+        _check(self.lib.pr_grad(self.h, _ptr(lam, self.iterate_numel), _ptr(gT, self.state_numel),
+                                _ptr(dldu0, self.state_numel), ctypes.byref(out)))
         return out.value
 
     def apply_fine(self, x, y, count: int, steps: int = 0):
-        _check(self.lib.pr_apply_fine(self.h, _ptr(x), _ptr(y), count, steps))
+        q = max(count, 0) * self.npts[0]
+        _check(self.lib.pr_apply_fine(self.h, _ptr(x, q, True), _ptr(y, q, True), count, steps))
 
     def apply_coarse(self, x, y, count: int) -> int:
         it = ctypes.c_longlong()
-        _check(self.lib.pr_apply_coarse(self.h, _ptr(x), _ptr(y), count, ctypes.byref(it)))
+        q = max(count, 0) * self.npts[0]
+        _check(self.lib.pr_apply_coarse(self.h, _ptr(x, q, True), _ptr(y, q, True), count, ctypes.byref(it)))
         return it.value
 
     def set_fine_shape(self, tb_depth: int, tile_rows: int, xpts: int = 0, problem: int = 0):
@@ -302,7 +348,7 @@ class Problem:
     def solve_batch(self, u0, lam, allow_notconv=False):
         """Batched synchronous solve; returns one Stats per problem."""
         arr = (pr_stats * self.nproblems)()
-        rc = _check(self.lib.pr_solve_sync(self.h, _ptr(u0), _ptr(lam), arr),
+        rc = _check(self.lib.pr_solve_sync(self.h, _ptr(u0, self.state_numel), _ptr(lam, self.iterate_numel), arr),
                     (PR_ENOTCONV,) if allow_notconv else ())
         return rc, [arr[b] for b in range(self.nproblems)]
 
@@ -334,6 +380,8 @@ def _torch_function():
 
         @staticmethod
         def forward(ctx, u0, nu, dim, n, T, nslices, dt_nominal, eps, driver):
+            if u0.numel() != n ** dim:
+                raise ValueError(f"u0 holds {u0.numel()} values, a {dim}D grid of side {n} has {n ** dim}")
             cfg = make_config(dim, n, float(nu), T, nslices, dt_nominal, eps=eps)
             prob = Problem(cfg, device=u0.device.index or 0)
             lam = torch.empty((nslices + 1,) + tuple(u0.shape), dtype=torch.float64, device=u0.device)

@@ -15,8 +15,9 @@
 // Publication: every slice owns a ring of R slots holding its newest
 // versions; the slot data is written by the team, then the team leader
 // stores the version number with agent-scope release semantics.  A reader
-// acquires the version, copies the slot, and re-reads the version: the copy
-// is valid if the writer cannot have started overwriting that slot meanwhile
+// acquires the version, copies the slot with the whole team, meets the team
+// at a barrier and re-reads the version: the copy is valid if the writer
+// cannot have started overwriting that slot before the last load returned
 // (at most R-2 newer versions published).  Per-slice headers (change of the
 // last update, accumulated change "drift", predecessor drift at the version
 // read) are updated under a sequence lock so that a monitor can take a
@@ -536,6 +537,11 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                 } else {
                     team_copy(tm, a.g, src, x_new);
                 }
+                // Ring slots are reused: the copy is valid only if the writer had
+                // not started on this slot again when the LAST load of every
+                // workgroup of the team had returned, so the version is re-read
+                // after a team barrier (scheduled reads keep every version).
+                if (!scheduled_reads(a.mode) && i > 1 && !team_sync(tm)) goto out;
                 long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                 if (leader) {
                     const double dr = a.slot_drift[(i - 1) * a.R + pv % a.R];

@@ -521,15 +521,24 @@ static int run_sweep(pr_problem *h, const Prob &P, SweepArgs a) {
 }
 
 // ------------------------------------------------------------------ create / destroy
-static int alloc_sync(pr_problem *h) {
+// The iterate-sized buffers of the synchronous driver: fine outputs v, coarse
+// values w and, when a slice takes several fine passes, their ping-pong buffer.
+static int alloc_sync_big(pr_problem *h) {
     const Prob &P = h->P[0];
     const size_t all = (size_t)(P.N + 1) * P.npts;
     int rc;
-    if ((rc = alloc_t(h, &h->v, all))) return rc;
-    if ((rc = alloc_t(h, &h->w, all))) return rc;
+    if (!h->v && (rc = alloc_t(h, &h->v, all))) return rc;
+    if (!h->w && (rc = alloc_t(h, &h->w, all))) return rc;
     const int passes = (P.m + fine_depth(P) - 1) / fine_depth(P);
-    if (P.dim > 1 && passes > 1)
+    if (P.dim > 1 && passes > 1 && !h->tmp)
         if ((rc = alloc_t(h, &h->tmp, all))) return rc;
+    return PR_OK;
+}
+
+static int alloc_sync(pr_problem *h) {
+    const Prob &P = h->P[0];
+    int rc;
+    if ((rc = alloc_sync_big(h))) return rc;
     if (P.dim > 1) {
         if ((rc = alloc_t(h, &h->wn, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_r, P.npts))) return rc;
@@ -787,10 +796,11 @@ extern "C" int pr_apply_coarse(pr_problem *h, const double *in, double *out, int
     double s = P.s, tol = P.cg_tol;
     int maxit = P.cg_maxit;
     CGWork wk{h->cg_r, h->cg_p0, h->cg_p1, h->red};
+    CGWork2 wk2{{h->cg_r, h->cg_r1}, {h->cg_p0, h->cg_p1}, h->red};
     unsigned *ctr = h->ctr;
     Control *ctl = h->ctl;
     unsigned long long *ci = h->iscal;
-    void *args[] = {&in, &out, &npts, &count, &g, &s, &tol, &maxit, &wk, &ctr, &ctl, &ci};
+    void *args[] = {&in, &out, &npts, &count, &g, &s, &tol, &maxit, &wk, &wk2, &ctr, &ctl, &ci};
     const void *fn = P.dim == 3 ? (const void *)k_coarse_cg_batch<3> : (const void *)k_coarse_cg_batch<2>;
     if ((rc = coop_launch(h, fn, h->sweep_grid, SWEEP_BLOCK, args))) return rc;
     if ((rc = check_control(h))) return rc;
@@ -832,6 +842,7 @@ extern "C" int pr_solve_fine(pr_problem *h, const double *u0, double *lam, pr_st
 
 // ------------------------------------------------------------------ synchronous Parareal
 static int batched_solve_sync(pr_problem *h, const double *u0, double *lam, pr_stats *st);
+static void free_async(pr_problem *h);
 
 extern "C" int pr_solve_sync(pr_problem *h, const double *u0, double *lam, pr_stats *st) {
     if (h && h->P.size() > 1) return batched_solve_sync(h, u0, lam, st);
@@ -840,7 +851,12 @@ extern "C" int pr_solve_sync(pr_problem *h, const double *u0, double *lam, pr_st
     const Prob &P = h->P[0];
     if (!u0 || !lam) return fail(PR_EINVAL, "NULL buffer");
     if (u0 == lam) return fail(PR_EINVAL, "u0 must not alias lambda_out");
-    if (!h->v) return fail(PR_EINVAL, "synchronous workspace missing");
+    if (!h->v) {
+        // an asynchronous solve released these buffers to fit its own (large
+        // 3D iterates): give its workspace back and allocate them again
+        if (h->aw_ready) free_async(h);
+        if ((rc = alloc_sync_big(h))) return rc;
+    }
     stats_reset(st);
     const long long np = P.npts;
     if ((rc = reset_fine_its(h))) return rc;

@@ -230,17 +230,23 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_cg(SweepArgs a) {
 }
 
 // Batch of independent coarse solves (tests and the apply entry point):
-// state c of the batch is solved by the whole grid, one after the other.
+// state c of the batch is solved by the whole grid, one after the other,
+// with the solver of the synchronous sweep (2D: the one-synchronisation CG;
+// 3D: the marching two-phase CG).
 template <int DIM>
 __global__ __launch_bounds__(SWEEP_THREADS) void k_coarse_cg_batch(const double *src, double *dst, long long npts,
                                                            int count, Geom g, double s, double tol,
-                                                           int maxit, CGWork wk, unsigned *ctr,
+                                                           int maxit, CGWork wk, CGWork2 wk2, unsigned *ctr,
                                                            Control *ctl, unsigned long long *cg_iters) {
     Team tm{ctr, ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
-    if (!team_setup(tm)) return;
+    if (!team_setup(tm, true)) return;
     unsigned long long its = 0;
     for (int c = 0; c < count; ++c) {
-        const int it = cg_team_dim<DIM, DIM == 3 ? 1 : 2>(tm, g, s, tol, maxit, src + c * npts, dst + c * npts, wk, -1.0);
+        int it;
+        if constexpr (DIM == 2)
+            it = team_cg<2>(tm, g, s, tol, maxit, src + c * npts, dst + c * npts, wk2, -1.0);
+        else
+            it = team_cg<3>(tm, g, s, tol, maxit, src + c * npts, dst + c * npts, wk, -1.0);
         if (it < 0) return;
         its += (unsigned long long)it;
         if (!team_sync(tm)) return;

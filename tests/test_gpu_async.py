@@ -287,3 +287,15 @@ def test_every_nth_slice_per_team_2d(mode):
     else:
         ls, ss = gpu_sync(p)
         assert st.iters == ss.iters and rel(lam.cpu().numpy(), ls) <= TOL
+
+
+def test_free_mode_ring_reuse_under_uneven_speeds_2d():
+    # three ring slots per slice: fast slices overwrite a slot soon after a
+    # slow successor starts copying it, so copies are re-checked after the
+    # whole team has finished them (a torn copy would leave the fixed point)
+    p = workloads.heat2d(n=96, nslices=12, T=1e-2)
+    d = disc_of(p)
+    delays = [(0 if i % 3 else 60) for i in range(p.nslices)]
+    prob, lam, st = solve(p, pr.PR_ASYNC_FREE, teams=12, delays=delays)
+    assert st.converged == 1
+    assert rel(lam, heat.serial_fine(p.u0, d.r, d.m, d.nslices)) <= TOL

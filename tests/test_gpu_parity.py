@@ -249,3 +249,16 @@ def test_abi_errors():
     prob = pr.Problem(pr.make_config(1, 10, 1.0, 1.0, 2, 1e-3))
     with pytest.raises(pr.PRError):
         prob.solve_sync(0, 0)
+    # buffers of the wrong size never reach a kernel
+    u0 = torch.zeros(10, dtype=torch.float64, device=DEV)
+    lam = torch.zeros(3 * 10, dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        prob.solve_sync(u0[:9], lam)
+    with pytest.raises(ValueError):
+        prob.solve_sync(u0, lam[:29])
+    with pytest.raises(ValueError):
+        prob.apply_fine(u0, lam, 2)
+    prob.solve_sync(u0, lam)
+    prob.apply_fine(lam, lam.clone(), 3)
+    prob.close()
+    prob.close()

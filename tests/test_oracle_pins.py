@@ -267,6 +267,25 @@ def test_spectral_parareal_sync_endpoints():
         assert np.max(np.abs(got - ser[i])) <= 1e-12 * np.max(np.abs(ser[i])), i
 
 
+def test_spectral_sync_change_vs_iterates_and_deltas():
+    # the closed-form change of one iteration against the difference of two
+    # closed-form iterates, and its max norm against the stencil/Thomas
+    # oracle's recorded changes on the 1D workload
+    p = workloads.heat1d()
+    d = _disc(p)
+    N = d.nslices
+    props = heat.Propagators(d)
+    res = parareal.parareal_sync(p.u0, props.F, props.G, N, eps=0.0)
+    for k in (1, 2, 5, 9, 14):
+        ch = spectral.parareal_sync_change(p.u0, d.r, d.m, d.s, k, range(N + 1))
+        diff = (spectral.parareal_sync(p.u0, d.r, d.m, d.s, k, range(N + 1))
+                - spectral.parareal_sync(p.u0, d.r, d.m, d.s, k - 1, range(N + 1)))
+        assert np.max(np.abs(ch - diff)) <= 1e-14 + 1e-12 * np.max(np.abs(ch)), k
+        assert not np.any(ch[:k])
+        got = float(np.max(np.abs(ch)))
+        assert abs(got - res.deltas[k - 1]) <= 1e-9 * res.deltas[k - 1] + 1e-15, k
+
+
 def test_spectral_propagators_vs_dense():
     rng = np.random.default_rng(5)
     u = rng.standard_normal((7, 7))
