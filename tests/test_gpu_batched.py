@@ -95,6 +95,10 @@ def test_full_batch_sampled():
         d = disc_of(p)
         assert st[b].converged == 1, b
         want = spectral.parareal_sync(p.u0, d.r, d.m, d.s, st[b].iters, range(p.nslices + 1))
-        assert rel(out[b], want) <= 1e-9, (b, rel(out[b], want))
+        e1 = rel(out[b], want)
         star = spectral.serial_fine(p.u0, d.r, d.m, d.nslices, slices=[d.nslices])[0]
-        assert rel(out[b][-1], star) <= 1e-9, b
+        e2 = rel(out[b][-1], star)
+        print(f"problem {b}: n={p.n} N={p.nslices} nu={p.nu:.3g} k={st[b].iters}: "
+              f"iterate err {e1:.2e}, u(T) err {e2:.2e}", flush=True)
+        assert e1 <= 1e-10, b
+        assert e2 <= 1e-10, b
