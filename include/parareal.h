@@ -206,6 +206,23 @@ int  pr_grad(pr_problem *h, const double *lambda, const double *gT,
 int  pr_apply_fine  (pr_problem *h, const double *in, double *out, int count, int steps);
 int  pr_apply_coarse(pr_problem *h, const double *in, double *out, int count, long long *cg_iters);
 
+/* Allocation-free variant of pr_apply_coarse, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  out[c] = G(in[c]), c < count, for the
+ * problem *cfg (2D or 3D, CG; the same solver and launch as pr_apply_coarse,
+ * hence the same bits), with no handle: every scratch buffer (CG vectors,
+ * reduction slots, team counters) lives in a fixed device array of the
+ * library, 32 MiB per device, held from the first call on a device until the
+ * process ends.  A state may hold at most 2^20 points (n <= 1024 in 2D,
+ * n <= 101 in 3D); larger states, 1D problems, aliasing or NULL buffers are
+ * PR_EINVAL.  device: HIP ordinal; stream: hipStream_t or NULL; in, out:
+ * count * n^dim doubles on that device, caller-owned; cg_iters (host, may be
+ * NULL): total CG iterations.  Calls no allocating routine; returns after the
+ * work has completed.  All calls on one device share the array: calls that
+ * overlap on one device (two threads, two streams) race and must not be made. */
+int  pr_apply_coarse_static(const pr_config *cfg, int device, void *stream, const double *in, double *out,
+                            int count, long long *cg_iters);
+
 /* Fine-kernel shape control (autotuner and tests): the supported shapes are
  * enumerated by index; pr_set_fine_shape selects one for a problem. */
 int  pr_fine_shape_count(int dim);

@@ -93,7 +93,7 @@ EXPORTS = [
     "pr_create", "pr_destroy", "pr_last_error", "pr_get_info", "pr_solve_sync",
     "pr_set_async_options", "pr_solve_async", "pr_solve_fine", "pr_grad",
     "pr_apply_fine", "pr_apply_coarse", "pr_fine_shape_count", "pr_fine_shape_get",
-    "pr_set_fine_shape", "pr_autotune", "pr_set_graph",
+    "pr_set_fine_shape", "pr_autotune", "pr_set_graph", "pr_apply_coarse_static",
 ]
 
 _lib = None
@@ -126,6 +126,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_double)]
     lib.pr_set_graph.argtypes = [P, ctypes.c_int]
+    lib.pr_apply_coarse_static.argtypes = [ctypes.POINTER(pr_config), ctypes.c_int, P, P, P, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_longlong)]
     _lib = lib
     return lib
 

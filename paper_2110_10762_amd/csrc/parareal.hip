@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "parareal.h"
@@ -806,6 +807,106 @@ extern "C" int pr_apply_coarse(pr_problem *h, const double *in, double *out, int
     if ((rc = check_control(h))) return rc;
     unsigned long long its = 0;
     HIPCHK(hipMemcpy(&its, h->iscal, sizeof its, hipMemcpyDeviceToHost));
+    if (cg_iters) *cg_iters = (long long)its;
+    return PR_OK;
+}
+
+// ------------------------------------------------------------------ coarse propagator without allocation
+// pr_apply_coarse_static keeps every scratch buffer of the coarse solve (CG
+// vectors, reduction slots, team counters, control words) in this file-scope
+// device array.  Each device the library runs on holds its own copy for the
+// life of the process; its device address is taken once per device with
+// hipGetSymbolAddress (the array's name is not a device address in host code).
+constexpr long long kStaticPts = 1ll << 20;          // largest state: 2^20 points
+constexpr long long kStaticRed = 2 * 4096;           // reduction slots (doubles)
+constexpr long long kStaticCtr = 4096 / 2;           // team counters: 4096 words
+constexpr long long kStaticCtl = 8;                  // Control + iteration counter
+constexpr long long kStaticDoubles = 4 * kStaticPts + kStaticRed + kStaticCtr + kStaticCtl;
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
+static std::mutex g_static_mu;
+static double *g_static_ptr[64] = {};
+static int g_static_grid[64] = {};
+
+// Device address of `scratch` on `device` (the current device), taken on the
+// first call on that device.
+static int static_scratch(int device, double **ptr, int *grid) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(PR_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        }
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, device));
+        int o2 = 0, o3 = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, (const void *)k_coarse_cg_batch<2>, SWEEP_BLOCK, 0));
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o3, (const void *)k_coarse_cg_batch<3>, SWEEP_BLOCK, 0));
+        if (std::min(o2, o3) < 1) return fail(PR_ENORESIDENT, "coarse solver kernel cannot be resident");
+        g_static_grid[device] = prop.multiProcessorCount;
+        g_static_ptr[device] = (double *)p;
+    }
+    *ptr = g_static_ptr[device];
+    *grid = g_static_grid[device];
+    return PR_OK;
+}
+
+extern "C" int pr_apply_coarse_static(const pr_config *cfg, int device, void *stream, const double *in,
+                                      double *out, int count, long long *cg_iters) {
+    if (cg_iters) *cg_iters = 0;
+    if (!cfg) return fail(PR_EINVAL, "cfg is NULL");
+    Prob P;
+    int rc = derive(*cfg, P);
+    if (rc) return rc;
+    if (P.dim == 1) return fail(PR_EINVAL, "pr_apply_coarse_static solves 2D and 3D problems (CG); 1D has no scratch");
+    if (P.npts > kStaticPts)
+        return fail(PR_EINVAL, "pr_apply_coarse_static: a state of %lld points exceeds its limit of %lld",
+                    (long long)P.npts, kStaticPts);
+    if (!in || !out) return fail(PR_EINVAL, "NULL buffer");
+    if (in == out) return fail(PR_EINVAL, "in and out must not alias");
+    if (count < 0) return fail(PR_EINVAL, "count must be >= 0");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev || device >= 64) return fail(PR_EINVAL, "device %d out of range", device);
+    HIPCHK(hipSetDevice(device));
+    double *base = nullptr;
+    int grid = 0;
+    if ((rc = static_scratch(device, &base, &grid))) return rc;
+    if (count == 0) return PR_OK;
+    hipStream_t st = (hipStream_t)stream;
+    double *r0 = base, *r1 = base + kStaticPts, *p0 = base + 2 * kStaticPts, *p1 = base + 3 * kStaticPts;
+    double *red = base + 4 * kStaticPts;
+    unsigned *ctr = (unsigned *)(red + kStaticRed);
+    Control *ctl = (Control *)(red + kStaticRed + kStaticCtr);
+    unsigned long long *ci = (unsigned long long *)(red + kStaticRed + kStaticCtr + 2);
+    static_assert(sizeof(Control) <= 2 * sizeof(double), "control words fit their slot");
+    static_assert(TEAM_CTR_WORDS <= 2 * kStaticCtr, "team counters fit their slot");
+    // counters, control words and the iteration count start at zero (a fill
+    // kernel, not a memset); the previous call's contents are overwritten
+    const int zw = (int)(2 * (kStaticCtr + kStaticCtl));
+    hipLaunchKernelGGL(k_zero_words, dim3((zw + 255) / 256), dim3(256), 0, st, ctr, zw);
+    HIPCHK(hipGetLastError());
+    long long npts = P.npts;
+    Geom g = P.g;
+    double s = P.s, tol = P.cg_tol;
+    int maxit = P.cg_maxit;
+    CGWork wk{r0, p0, p1, red};
+    CGWork2 wk2{{r0, r1}, {p0, p1}, red};
+    void *args[] = {&in, &out, &npts, &count, &g, &s, &tol, &maxit, &wk, &wk2, &ctr, &ctl, &ci};
+    const void *fn = P.dim == 3 ? (const void *)k_coarse_cg_batch<3> : (const void *)k_coarse_cg_batch<2>;
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(SWEEP_BLOCK), args, 0, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PR_ENORESIDENT, "cooperative launch of %d workgroups failed: %s", grid, hipGetErrorString(e));
+    }
+    Control c;
+    unsigned long long its = 0;
+    HIPCHK(hipMemcpyAsync(&c, ctl, sizeof c, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&its, ci, sizeof its, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (c.abort || c.error) return fail(PR_ETIMEOUT, "a bounded device-side wait ran out (error %d)", c.error);
     if (cg_iters) *cg_iters = (long long)its;
     return PR_OK;
 }
