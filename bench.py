@@ -403,12 +403,15 @@ def main():
 
     # ---- roofline objects (algorithmic bytes per launch / live event durations)
     # Algorithmic bytes per point: F pass 16 (read + write the state).  2D
-    # CG (sync sweep and async teams; products recomputed from r and p):
-    # iteration 48 (reads r, p_old, x; writes p, x, r'), set-up 24 (read b,
-    # write x, r0).  Correction 48 (read v, w_new, w_old, lambda_old, write
-    # lambda, w).
+    # preconditioned CG (sync sweep and async teams): iteration 96 (reads r,
+    # w, s, x, u, p; writes the same six), set-up 48 (read b, write x, r0;
+    # read r0, write u0, w0).  Unpreconditioned 2D CG (cg_precond = -1;
+    # products recomputed from r and p): iteration 48 (reads r, p_old, x;
+    # writes p, x, r'), set-up 24.  Correction 48 (read v, w_new, w_old,
+    # lambda_old, write lambda, w).
     D = info.tb_depth
     passes = -(-m // D)
+    cg_it_b, cg_set_b = (96.0, 48.0) if info.cg_precond else (48.0, 24.0)
     fine_kernel = fine_kernel_name(info)
     rl = {}
     if rec["sync"]:
@@ -421,10 +424,10 @@ def main():
                       "launches": f_launches, "avg_launch_ms": f_ms / f_launches,
                       "glups": sum(x["fine_lups"] for x in s) / (f_ms * 1e-3) / 1e9}
         c_ms = sum(x["coarse_ms"] for x in s)
-        c_bytes = sum(x["cg_iters"] * 48.0 * npts + x["g_solves"] * 24.0 * npts
+        c_bytes = sum(x["cg_iters"] * cg_it_b * npts + x["g_solves"] * cg_set_b * npts
                       + (x["g_solves"] + x["g_skipped"]) * 48.0 * npts for x in s)
         c_launches = sum(x["iters"] + 1 for x in s)
-        rl["sweep"] = {"kernel": "k_sweep_cg", "bound": "hbm", "achieved": c_bytes / (c_ms * 1e-3) / 1e9,
+        rl["sweep"] = {"kernel": "k_sweep_cg<2,true>" if info.cg_precond else "k_sweep_cg<2,false>", "bound": "hbm", "achieved": c_bytes / (c_ms * 1e-3) / 1e9,
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "launches": c_launches,
                        "avg_launch_ms": c_ms / c_launches}
     if rec["async"]:
@@ -436,9 +439,10 @@ def main():
             upd = x["kernel_updates"]
             solves = x["g_solves"] - N          # minus the initial coarse sweep
             # per update: F passes, predecessor copy 16, correction + next slot 48
-            a_bytes += (upd * (a_passes * 16.0 + 16.0 + 48.0) + x["kernel_cg_iters"] * 48.0
-                        + solves * 24.0) * npts
-        rl["async"] = {"kernel": f"k_async<2,2,0,{ASYNC_DEPTH}>", "bound": "hbm",
+            a_bytes += (upd * (a_passes * 16.0 + 16.0 + 48.0) + x["kernel_cg_iters"] * cg_it_b
+                        + solves * cg_set_b) * npts
+        rl["async"] = {"kernel": f"k_async<2,2,0,{ASYNC_DEPTH},false,{'true' if info.cg_precond else 'false'}>",
+                       "bound": "hbm",
                        "achieved": a_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "launches": len(a), "avg_launch_ms": k_ms / len(a)}
     same_sources = sources_digest() == PROFILED_SOURCES

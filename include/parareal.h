@@ -88,6 +88,9 @@ typedef struct pr_config {
                             first shape matching every nonzero (tb_depth, tile_rows,
                             fine_xpts) is used; none matching is PR_EINVAL. */
     int    fine;         /* PR_FINE_*: the fine propagator's time stepping */
+    int    cg_precond;   /* 2D CG (coarse solves): degree of its Chebyshev polynomial
+                            preconditioner; 0 = default (4), -1 = none (plain CG).  The
+                            preconditioner changes iterates at the tolerance level only. */
 } pr_config;
 
 /* Derived discretisation of one problem (read-only view). */
@@ -100,6 +103,7 @@ typedef struct pr_info {
     long long offset;    /* index of this problem's lambda_0[0] in a concatenated iterate */
     int    tb_depth, tile_rows;   /* fine-kernel shape in use */
     int    xpts, sliding;         /* its x points per lane; 1 for a sliding window */
+    int    cg_precond;            /* degree of the CG preconditioner in use (2D), 0 = none */
 } pr_info;
 
 typedef struct pr_stats {
@@ -161,6 +165,17 @@ typedef struct pr_async_opts {
                                 (0 = none; at most 1e7) */
     int slice_blocks;        /* which slices a team holds: 1 = a contiguous block, 2 = every
                                 teams-th slice; 0 = default (blocks) */
+    /* Failure injection (FREE and EXACT modes; NULL = none).  Section 2.1's
+       assumptions (every slice updates infinitely often, bounded delays)
+       still hold under both, so the iteration reaches the same fixed point. */
+    const int *drop_every;   /* optional host array [N]: slice i's update number j is
+                                computed but not published (a lost message) when
+                                drop_every[i] >= 2 divides j; 0 = never.  A slice whose
+                                last value was lost does not idle: it updates again. */
+    const int *reset_after;  /* optional host array [N], FREE mode only: slice i loses its
+                                state once, before update reset_after[i] + 1, and starts
+                                again from the initial guess (F from lambda_{i-1}^0,
+                                w_old = lambda_i^0); < 0 = never */
 } pr_async_opts;
 
 /* Create a handle for one problem (nproblems == 1) or a batch of independent
@@ -212,7 +227,7 @@ int  pr_apply_coarse(pr_problem *h, const double *in, double *out, int count, lo
  * problem *cfg (2D or 3D, CG; the same solver and launch as pr_apply_coarse,
  * hence the same bits), with no handle: every scratch buffer (CG vectors,
  * reduction slots, team counters) lives in a fixed device array of the
- * library, 32 MiB per device, held from the first call on a device until the
+ * library, 64 MiB per device, held from the first call on a device until the
  * process ends.  A state may hold at most 2^20 points (n <= 1024 in 2D,
  * n <= 101 in 3D); larger states, 1D problems, aliasing or NULL buffers are
  * PR_EINVAL.  device: HIP ordinal; stream: hipStream_t or NULL; in, out:

@@ -142,6 +142,23 @@ class AsyncReplay:
             self.final_from[i] = self.newest(i)
         self.events.append((i, j))
 
+    def reset(self, i: int) -> None:
+        """Slice i loses its local state (a restarted processor): its next
+        update starts again from the initial guess, F from the predecessor's
+        coarse guess lambda_{i-1}^0 and w_old = G(lambda_{i-1}^0) = lambda_i^0,
+        as at the start of Algorithm 2.  Its published versions and k_i stay.
+        The finite-termination bookkeeping of this slice restarts: it is final
+        again only after an update whose both inputs are final (Section 3.2)."""
+        if not 1 <= i <= self.N:
+            raise ValueError("slice index out of range")
+        self.f_ver[i] = 0
+        self.w_old[i] = self.versions[i][0].copy()
+        self.last_f_ver[i] = -1
+        # its next versions are not final, nor those of any successor that
+        # reads them: the final marks downstream are re-established later
+        for j in range(i, self.N + 1):
+            self.final_from[j] = -1
+
     def current(self) -> np.ndarray:
         return np.stack([self.versions[i][-1] for i in range(self.N + 1)])
 
@@ -192,18 +209,24 @@ def replay(u0, F, G, nslices, schedule: Iterable[Tuple[int, int]]) -> AsyncRepla
 
 def run_random(u0, F, G, nslices: int, seed: int, max_delay: int = 3,
                eps: float = 0.0, max_rounds: int = 10_000,
-               exact: bool = False) -> AsyncReplay:
+               exact: bool = False, resets=None) -> AsyncReplay:
     """Fair, bounded-delay random schedule (the two assumptions of Section 2.1).
 
     Rounds: each round updates every slice once in a random order (fairness),
     and each coarse solve reads a uniformly random version among the newest
     ``max_delay + 1`` that are allowed (bounded delay).  Stops by the tolerance
-    rule (eps > 0) or the exact rule (exact=True), else after max_rounds."""
+    rule (eps > 0) or the exact rule (exact=True), else after max_rounds.
+    resets: {slice: k} resets that slice (AsyncReplay.reset) once, just
+    before its update number k + 1."""
     rng = np.random.default_rng(seed)
     st = AsyncReplay(u0, F, G, nslices)
+    pending = dict(resets or {})
     for _ in range(max_rounds):
         for i in rng.permutation(np.arange(1, nslices + 1)):
             i = int(i)
+            if pending.get(i) == st.k[i]:
+                st.reset(i)
+                del pending[i]
             hi = st.newest(i - 1)
             lo = max(st.f_ver[i], hi - max_delay)
             j = int(rng.integers(lo, hi + 1))

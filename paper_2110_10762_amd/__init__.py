@@ -46,7 +46,7 @@ class pr_config(ctypes.Structure):
         ("coarse", ctypes.c_int), ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
         ("eps", ctypes.c_double), ("kmax", ctypes.c_int), ("tb_depth", ctypes.c_int),
         ("tile_rows", ctypes.c_int), ("coarse_increment", ctypes.c_int),
-        ("fine_xpts", ctypes.c_int), ("fine", ctypes.c_int),
+        ("fine_xpts", ctypes.c_int), ("fine", ctypes.c_int), ("cg_precond", ctypes.c_int),
     ]
 
 
@@ -56,7 +56,7 @@ class pr_info(ctypes.Structure):
         ("h", ctypes.c_double), ("r", ctypes.c_double), ("s", ctypes.c_double),
         ("npts", ctypes.c_longlong), ("offset", ctypes.c_longlong),
         ("tb_depth", ctypes.c_int), ("tile_rows", ctypes.c_int),
-        ("xpts", ctypes.c_int), ("sliding", ctypes.c_int),
+        ("xpts", ctypes.c_int), ("sliding", ctypes.c_int), ("cg_precond", ctypes.c_int),
     ]
 
 
@@ -86,6 +86,7 @@ class pr_async_opts(ctypes.Structure):
         ("schedule", ctypes.POINTER(ctypes.c_int)), ("delay_spins", ctypes.POINTER(ctypes.c_int)),
         ("time_limit_s", ctypes.c_double), ("latency_us", ctypes.c_double),
         ("slice_blocks", ctypes.c_int),
+        ("drop_every", ctypes.POINTER(ctypes.c_int)), ("reset_after", ctypes.POINTER(ctypes.c_int)),
     ]
 
 
@@ -172,9 +173,9 @@ def _ptr(x, numel: Optional[int] = None, at_least: bool = False) -> int:
 
 def make_config(dim, n, nu, T, nslices, dt_nominal, coarse=PR_COARSE_AUTO, cg_tol=1e-12,
                 cg_maxit=0, eps=1e-10, kmax=0, tb_depth=0, tile_rows=0,
-                coarse_increment=0, fine_xpts=0, fine=0) -> pr_config:
+                coarse_increment=0, fine_xpts=0, fine=0, cg_precond=0) -> pr_config:
     return pr_config(dim, n, nu, T, nslices, dt_nominal, coarse, cg_tol, cg_maxit, eps, kmax,
-                     tb_depth, tile_rows, coarse_increment, fine_xpts, fine)
+                     tb_depth, tile_rows, coarse_increment, fine_xpts, fine, cg_precond)
 
 
 def config_of(problem, **over) -> pr_config:
@@ -301,7 +302,9 @@ class Problem:
     def set_async_options(self, mode=PR_ASYNC_FREE, teams=0, max_local_iters=0,
                           schedule: Optional[Sequence[int]] = None,
                           delay_spins: Optional[Sequence[int]] = None,
-                          time_limit_s: float = 0.0, latency_us: float = 0.0, slice_blocks: int = 0):
+                          time_limit_s: float = 0.0, latency_us: float = 0.0, slice_blocks: int = 0,
+                          drop_every: Optional[Sequence[int]] = None,
+                          reset_after: Optional[Sequence[int]] = None):
         o = pr_async_opts()
         o.mode, o.teams, o.max_local_iters = mode, teams, max_local_iters
         o.time_limit_s = time_limit_s
@@ -316,6 +319,14 @@ class Problem:
             arr = (ctypes.c_int * len(delay_spins))(*delay_spins)
             keep.append(arr)
             o.delay_spins = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int))
+        for name, vals in (("drop_every", drop_every), ("reset_after", reset_after)):
+            if vals is not None:
+                n = self.cfgs[0].nslices
+                if len(vals) != n:
+                    raise ValueError(f"{name} needs one entry per slice ({n})")
+                arr = (ctypes.c_int * n)(*vals)
+                keep.append(arr)
+                setattr(o, name, ctypes.cast(arr, ctypes.POINTER(ctypes.c_int)))
         _check(self.lib.pr_set_async_options(self.h, ctypes.byref(o)))
 
     def grad(self, lam, gT, dldu0) -> float:

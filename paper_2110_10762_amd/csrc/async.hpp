@@ -39,6 +39,7 @@
 #pragma once
 #include "fine.hpp"
 #include "coarse.hpp"
+#include "pcg.hpp"
 #include "implicit.hpp"
 
 namespace pr {
@@ -67,7 +68,8 @@ struct SliceLoc {     // team-private control state of a slice (leader only)
     int f_final;      // x_old is the predecessor's final value (EXACT)
     int stale_streak; // consecutive updates with a stale coarse input
     int done;
-    int pad0, pad1;
+    int unpub;        // its last computed value was not published (a lost message)
+    int reset_done;   // the injected reset has happened
 };
 
 struct AsyncWork {
@@ -81,6 +83,9 @@ struct AsyncWork {
     long long *tbc = nullptr;
     double *tred = nullptr;
     double *cgr = nullptr, *cgr1 = nullptr, *cgp0 = nullptr, *cgp1 = nullptr, *cgb = nullptr;
+    double *cgw0 = nullptr, *cgw1 = nullptr, *cgs0 = nullptr, *cgs1 = nullptr;   // 2D preconditioned CG
+    int *drop = nullptr, *reset = nullptr;   // failure injection, [N+1] each
+    double *lam0 = nullptr;                  // [(N+1) npts] initial iterate (resets only)
     unsigned long long *counters = nullptr;
     unsigned long long *pub_t = nullptr;   // [(N+1) R] publication time of each slot's version
     int *pipe = nullptr;                   // PIPELINED: [N+2] publications per version, then K*
@@ -106,6 +111,9 @@ struct AsyncArgs {
     double *slot_drift;      // [(N+1) R]
     const int *sched;        // REPLAY: [N][L]
     const int *delay;        // [N+1] or NULL
+    const int *drop;         // [N+1] or NULL: update j of slice i is not published if drop[i] | j
+    const int *reset;        // [N+1] or NULL: slice i starts again from lambda^0 before update reset[i] + 1
+    const double *lam0;      // [(N+1) npts] the initial iterate, when resets are injected
     unsigned long long *pub_t;    // [(N+1) R] wall-clock time each slot's version was published
     unsigned long long lat;       // ticks after publication before a version may be read
     int *pipe;                    // PIPELINED: [N+1] publication counts per version, [N+1] = K*
@@ -119,8 +127,9 @@ struct AsyncArgs {
     const int *team_of, *rank_of, *tsize;   // per workgroup / per team
     unsigned *tctr;          // [nteams * 16]
     long long *tbc;          // [nteams * 16] leader broadcasts
-    double *tred;            // [nteams * 6 * maxtsz]
+    double *tred;            // [nteams * 8 * maxtsz]
     double *cgr, *cgr1, *cgp0, *cgp1;   // [nteams * cgs]
+    double *cgw0, *cgw1, *cgs0, *cgs1;  // [nteams * cgs], 2D preconditioned CG only
     long long cgs;               // per-team stride of the CG vectors
     Control *ctl;
     unsigned long long *counters;   // cg iterations, coarse solves, skipped solves, copy retries, idle rounds
@@ -317,7 +326,7 @@ __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const do
 }
 
 // ---- coarse solve of one state by a team; returns iterations or -1
-template <int DIM, int RR>
+template <int DIM, int RR, bool PCG>
 __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double *x, const CGWork &wk,
                            const CGWork2 &wk2, double abs_thresh2 = -1.0) {
     if constexpr (DIM == 1) {
@@ -347,7 +356,14 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
         // two-phase CG with marching phases (26.6 s for the 3D workload with
         // one chunk per wave in flight, 11.7 s with four, 10.7 s marching).
         int it;
-        if constexpr (DIM == 2)
+        if constexpr (DIM == 2 && PCG) {
+            // the preconditioned CG (marching sweeps of a whole iteration)
+            const long long o = (long long)a.team_of[blockIdx.x] * a.cgs;
+            const CGWorkP wkp{{wk2.r[0], wk2.r[1]}, {a.cgw0 + o, a.cgw1 + o}, {a.cgs0 + o, a.cgs1 + o},
+                              wk2.p[0], wk2.p[1], wk2.red};
+            it = cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_TEAM, 1>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wkp,
+                                                           abs_thresh2);
+        } else if constexpr (DIM == 2)
             it = cg_team_2d_r<true>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk2, abs_thresh2);
         else
             it = cg_team_dim<DIM, 4, DIM == 3>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
@@ -363,7 +379,7 @@ enum { ACT_IDLE = 0, ACT_UPDATE = 1, ACT_DONE = 2 };
 // would be copied to scratch.  XP: x points per lane of F; RR: points per
 // lane in 1D, rows per strip in 3D (2D takes its fine segment length at run
 // time, RR = 0); D: fine steps per pass.
-template <int DIM, int XP, int RR, int D, bool IMPL = false>
+template <int DIM, int XP, int RR, int D, bool IMPL = false, bool PCG = false>
 // Two workgroups per CU in 2D and 3D: 256 registers per lane, room for the
 // two chunks in flight of the 2D coarse solver without spills.
 __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncArgs *__restrict__ ap) {
@@ -374,7 +390,7 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
     Team tm{a.tctr + (long long)team * team_counter_words(a.maxtsz), a.ctl, a.tsize[team], rank, 0u};
     if (!team_setup(tm)) return;
     long long *bc = a.tbc + team * 16;
-    double *const tred = a.tred + (long long)team * 6 * a.maxtsz;
+    double *const tred = a.tred + (long long)team * 8 * a.maxtsz;
     CGWork wk{a.cgr + (long long)team * a.cgs, a.cgp0 + (long long)team * a.cgs,
               a.cgp1 + (long long)team * a.cgs, tred};
     const CGWork2 wk2{{wk.r, a.cgr1 + (long long)team * a.cgs}, {wk.p0, wk.p1}, tred};
@@ -446,9 +462,18 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                         }
                     }
                 } else {
+                    if (a.reset && !L.reset_done && a.reset[i] >= 0 && a.hdr[i].k == a.reset[i]) {
+                        // the slice loses its state: x_old, w_old go back to the
+                        // initial guess (copied by the team below)
+                        L.reset_done = 1;
+                        L.f_ver = 0;
+                        L.f_final = (i == 1) ? 1 : 0;
+                        L.stale_streak = 0;
+                        b[6] = 1;
+                    }
                     pv = (i == 1) ? 0 : visible_version(a, i - 1);
                     const bool stale = (pv == L.f_ver);
-                    if (a.idle_skip && stale && L.stale_streak >= 1) {
+                    if (a.idle_skip && stale && L.stale_streak >= 1 && !L.unpub) {
                         // Its last update already read this predecessor version, so
                         // another update would republish F(x_old) unchanged: record
                         // that (zero) change once, then wait.  Retire if nothing new
@@ -493,6 +518,11 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
             double *w_old = a.W + wo * all + i * np;
             double *w_new = a.W + (wo ^ 1) * all + i * np;
             double *v = a.V + i * np;
+            if (b[6]) {   // injected reset: start again from the initial guess
+                team_copy(tm, a.g, a.lam0 + (i - 1) * np, x_old);
+                if (!a.incr) team_copy(tm, a.g, a.lam0 + i * np, w_old);
+                if (!team_sync(tm)) goto out;
+            }
             // ---------------- v = F(x_old)
             tp = wall_clock64();
             if (!team_fine<DIM, XP, RR, D, IMPL>(tm, a, x_old, v, a.S ? a.S + i * np : nullptr, wk, wk2,
@@ -581,7 +611,8 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                     if (!team_reduce<false>(tm, nrm_part, wk.red, nrm, lds)) goto out;
                     thr = a.cg_tol * a.cg_tol * nrm;
                 }
-                const int it = team_coarse<DIM, RR>(tm, a, a.incr ? dbuf : x_new, a.incr ? ybuf : w_new, wk, wk2, thr);
+                const int it = team_coarse<DIM, RR, PCG>(tm, a, a.incr ? dbuf : x_new, a.incr ? ybuf : w_new, wk, wk2,
+                                                         thr);
                 if (it < 0) goto out;
                 cg_its += (unsigned long long)it;
                 ++g_solves;
@@ -618,13 +649,21 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                 SliceLoc &L = a.loc[i];
                 SliceHdr *h = &a.hdr[i];
                 const double drift = h->drift + delta;
-                a.slot_drift[i * a.R + nslot] = drift;
                 const double sref = stale ? h->stale_ref : drift_read;
                 const int gf = stale ? L.f_final : g_final;
                 int ff = h->final_from;
                 if (ff < 0 && L.f_final && gf) ff = myver + 1;
-                st_relaxed_u64(&a.pub_t[i * a.R + nslot], wall_clock64());   // ordered by the publication
-                hdr_publish(h, myver + 1, h->k + 1, pv, ff, delta, drift, sref);
+                // injected message loss: the update counts, its value is not published
+                const bool lost = a.drop && a.drop[i] > 0 && (h->k + 1) % a.drop[i] == 0;
+                if (lost) {
+                    hdr_publish(h, myver, h->k + 1, h->g_ver, h->final_from, h->delta, h->drift, h->stale_ref);
+                    ff = -1;
+                } else {
+                    a.slot_drift[i * a.R + nslot] = drift;
+                    st_relaxed_u64(&a.pub_t[i * a.R + nslot], wall_clock64());   // ordered by the publication
+                    hdr_publish(h, myver + 1, h->k + 1, pv, ff, delta, drift, sref);
+                }
+                L.unpub = lost ? 1 : 0;
                 if (a.mode == AMODE_PIPELINED) {
                     // version v is complete once slices v..N have published it; the
                     // first complete version with a change below eps (or v = N, or

@@ -238,14 +238,65 @@ struct ShapeSW {
     static constexpr int PF = XP >= 4 ? 4 : 8;   // input rows in flight ahead of the window
 };
 
+// Strips of a sliding-window pass.  A wave holds C = 64 XP columns; after D
+// levels the values in its outer D columns on a side are invalid, unless that
+// side lies on the domain boundary: there the lane shift's zero fill is the
+// Dirichlet ghost value itself, at every level.  A grid at least C wide takes
+// one strip flush with each boundary (C - D owned columns each) and interior
+// strips of C - 2D between them (1024 columns: 120 + 7 x 112 + 120, nine
+// strips instead of ten); a narrower grid reads the odd extension on both
+// sides of every strip.  Every point is computed alike in either layout.
+// (C = 64 XP columns per wave, D levels)
+__host__ __device__ inline int sw_strip_count(int C, int D, int n) {
+    const int W = C - 2 * D, WB = C - D;
+    if (n < C) return (n + W - 1) / W;
+    if (n <= 2 * WB) return n == C ? 1 : 2;
+    return 2 + (n - 2 * WB + W - 1) / W;
+}
+
+template <int XP, int D>
+__host__ __device__ inline int sw_strips(int n) {
+    return sw_strip_count(WAVE * XP, D, n);
+}
+
+// First column x0 of strip sx's wave (negative: odd extension) and the lane
+// columns [lo, hi) it owns.
+template <int XP, int D>
+__device__ __forceinline__ void sw_strip(int sx, int n, int &x0, int &lo, int &hi) {
+    constexpr int C = WAVE * XP, W = C - 2 * D, WB = C - D;
+    if (n < C) {
+        x0 = sx * W - D;
+        lo = D;
+        hi = min(D + W, n - x0);
+        return;
+    }
+    const int ns = sw_strips<XP, D>(n);
+    if (ns == 1 || sx == 0) {
+        x0 = 0;
+        lo = 0;
+        hi = ns == 1 ? C : WB;
+        return;
+    }
+    const int start = WB + (sx - 1) * W;   // first owned column
+    if (sx == ns - 1) {
+        x0 = n - C;
+        lo = start - x0;
+        hi = C;
+        return;
+    }
+    x0 = start - D;
+    lo = D;
+    hi = D + W;
+}
+
 // PF: input rows in flight ahead of the window (more hides HBM latency, fewer
 // saves registers).
 template <int XP, int D, int PF, bool VEC>
 __device__ __forceinline__ void fine2d_sw_body(const double *__restrict__ src, double *__restrict__ dst, int n,
                                                double r, int steps, int sx, int ya, int yb, bool upward) {
-    constexpr int W = ShapeSW<XP, D>::W;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int x0 = sx * W - D;
+    int x0, lo, hi;
+    sw_strip<XP, D>(sx, n, x0, lo, hi);
     unsigned xo[XP];   // byte offsets of the lane's columns (reflected)
     double xs[XP];
     bool own[XP];
@@ -253,7 +304,7 @@ __device__ __forceinline__ void fine2d_sw_body(const double *__restrict__ src, d
     for (int e = 0; e < XP; ++e) {
         const int lx = lane * XP + e;
         xo[e] = (unsigned)reflect(x0 + lx, n, xs[e]) * 8u;
-        own[e] = lx >= D && lx < D + W && x0 + lx < n;
+        own[e] = lx >= lo && lx < hi;
     }
     double rt[D];
 #pragma unroll
@@ -325,9 +376,9 @@ __device__ __forceinline__ void fine2d_sw_body(const double *__restrict__ src, d
 template <int XP, int D, int PF = ShapeSW<XP, D>::PF, bool VEC_OK = true>
 __device__ __forceinline__ void fine2d_sw(const double *__restrict__ src, double *__restrict__ dst, int n,
                                           double r, int steps, int sx, int ya, int yb, bool upward) {
-    constexpr int W = ShapeSW<XP, D>::W;
-    const int x0 = sx * W - D;
     if constexpr (VEC_OK && XP % 2 == 0 && D % 2 == 0) {
+        int x0, lo, hi;
+        sw_strip<XP, D>(sx, n, x0, lo, hi);
         if (x0 >= 0 && x0 + WAVE * XP <= n && (n & 1) == 0) {
             fine2d_sw_body<XP, D, PF, true>(src, dst, n, r, steps, sx, ya, yb, upward);
             return;

@@ -101,6 +101,7 @@ struct Prob {
     int cg_maxit, kmax;
     double eps;
     int fine;              // FINE_EXPLICIT, FINE_BACKWARD_EULER or FINE_TRAPEZOIDAL
+    bool pcg;              // 2D coarse solves by the preconditioned CG
 };
 
 struct Buf {
@@ -118,6 +119,7 @@ struct pr_problem {
     double *v = nullptr, *w = nullptr, *tmp = nullptr, *wn = nullptr, *d0 = nullptr, *d1 = nullptr;
     double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *red = nullptr;
     double *cg_r1 = nullptr;   // second residual buffer of the 2D one-synchronisation CG
+    double *cg_w0 = nullptr, *cg_w1 = nullptr, *cg_s0 = nullptr, *cg_s1 = nullptr;   // 2D preconditioned CG
     double *inv_tab = nullptr;        // 1D Thomas factors, padded
     double *inv_tab_f = nullptr;      // 1D Thomas factors of an implicit fine step (s = theta r)
     // implicit fine steps on many states (2D/3D): per-team tmp, rhs, CG set
@@ -136,6 +138,7 @@ struct pr_problem {
     pr_async_opts aopt{};
     std::vector<int> sched;           // copy of the replay schedule
     std::vector<int> delays;
+    std::vector<int> drops, resets;   // failure injection, [N+1] each (empty: none)
     AsyncWork aw{};
     bool aw_ready = false;
     // batched workspace
@@ -209,6 +212,9 @@ static int derive(const pr_config &c, Prob &P) {
     P.r = P.nu * P.dt / (P.h * P.h);
     P.s = P.nu * P.dT / (P.h * P.h);
     P.fine = c.fine;
+    if (c.cg_precond != 0 && c.cg_precond != -1 && c.cg_precond != PCG_DEGREE)
+        return fail(PR_EINVAL, "cg_precond: 0 (default), -1 (none) or %d (got %d)", PCG_DEGREE, c.cg_precond);
+    P.pcg = c.dim == 2 && c.cg_precond >= 0;
     if (P.fine == FINE_EXPLICIT && P.r > 0.5 / P.dim * (1.0 + 1e-12))
         return fail(PR_EUNSTABLE, "explicit Euler unstable: r = %.6g > 1/(2d) = %.6g", P.r, 0.5 / P.dim);
     P.g = make_geom(P.dim, P.n);
@@ -246,8 +252,7 @@ static void launch2d(hipStream_t st, const double *src, double *dst, long long s
 template <int XP, int D>
 static void launch2d_sw(hipStream_t st, const double *src, double *dst, long long ss, long long ds, int n,
                         double r, int steps, int count, int ry) {
-    constexpr int W = ShapeSW<XP, D>::W;
-    const int nsx = (n + W - 1) / W, nsy = (n + ry - 1) / ry;
+    const int nsx = sw_strips<XP, D>(n), nsy = (n + ry - 1) / ry;
     const long long waves = (long long)nsx * nsy * count;
     const int nblk = (int)((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
     const int grid = 8 * ((nblk + 7) / 8);
@@ -491,6 +496,7 @@ static SweepArgs sweep_args(pr_problem *h, const Prob &P, double *lam) {
     a.cg_maxit = P.cg_maxit;
     a.wk = CGWork{h->cg_r, h->cg_p0, h->cg_p1, h->red};
     a.wk2 = CGWork2{{h->cg_r, h->cg_r1}, {h->cg_p0, h->cg_p1}, h->red};
+    a.wkp = CGWorkP{{h->cg_r, h->cg_r1}, {h->cg_w0, h->cg_w1}, {h->cg_s0, h->cg_s1}, h->cg_p0, h->cg_p1, h->red};
     a.ctr = h->ctr;
     a.ctl = h->ctl;
     return a;
@@ -517,8 +523,9 @@ static int run_sweep(pr_problem *h, const Prob &P, SweepArgs a) {
     rc = zero_words(h, h->ctl, sizeof(Control) / 4);
     if (rc) return rc;
     void *args[] = {&a};
-    const void *fn = P.dim == 3 ? (const void *)k_sweep_cg<3> : (const void *)k_sweep_cg<2>;
-    return coop_launch(h, fn, h->sweep_grid, SWEEP_BLOCK, args);
+    const void *fn = P.dim == 3 ? (const void *)k_sweep_cg<3>
+                                : (P.pcg ? (const void *)k_sweep_cg<2, true> : (const void *)k_sweep_cg<2>);
+    return coop_launch(h, fn, h->sweep_grid, sweep_threads(P.dim == 2 && P.pcg), args);
 }
 
 // ------------------------------------------------------------------ create / destroy
@@ -546,6 +553,10 @@ static int alloc_sync(pr_problem *h) {
         if ((rc = alloc_t(h, &h->cg_p0, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_p1, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_r1, P.npts))) return rc;
+        if ((rc = alloc_t(h, &h->cg_w0, P.npts))) return rc;
+        if ((rc = alloc_t(h, &h->cg_w1, P.npts))) return rc;
+        if ((rc = alloc_t(h, &h->cg_s0, P.npts))) return rc;
+        if ((rc = alloc_t(h, &h->cg_s1, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->d0, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->d1, P.npts))) return rc;
     }
@@ -621,9 +632,12 @@ extern "C" int pr_create(const pr_config *cfgs, int nproblems, int device, void 
     if ((rc = alloc_t(h, &h->iscal, 16))) return bail(rc);
     int occ = 0;
     int occ2 = 0;
+    int occ3 = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_sweep_cg<3>, SWEEP_BLOCK, 0) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, (const void *)k_sweep_cg<2>, SWEEP_BLOCK, 0) != hipSuccess ||
-        std::min(occ, occ2) < 1)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, (const void *)k_sweep_cg<2, true>, PCG_THREADS, 0) !=
+            hipSuccess ||
+        std::min({occ, occ2, occ3}) < 1)
         return bail(fail(PR_EHIP, "occupancy query failed"));
     h->sweep_grid = h->ncu * std::min(occ, 1);
     h->red_slots = 2 * 4096;
@@ -660,6 +674,7 @@ extern "C" int pr_get_info(const pr_problem *h, int problem, pr_info *out) {
     out->npts = P.npts;
     out->offset = P.off_lam;
     out->sliding = 0;
+    out->cg_precond = (P.pcg && h->P.size() == 1) ? PCG_DEGREE : 0;   // batches keep the plain CG
     if (P.dim == 2) {
         out->tb_depth = kShapes2D[P.shape].d;
         out->tile_rows = kShapes2D[P.shape].r;
@@ -798,12 +813,14 @@ extern "C" int pr_apply_coarse(pr_problem *h, const double *in, double *out, int
     int maxit = P.cg_maxit;
     CGWork wk{h->cg_r, h->cg_p0, h->cg_p1, h->red};
     CGWork2 wk2{{h->cg_r, h->cg_r1}, {h->cg_p0, h->cg_p1}, h->red};
+    CGWorkP wkp{{h->cg_r, h->cg_r1}, {h->cg_w0, h->cg_w1}, {h->cg_s0, h->cg_s1}, h->cg_p0, h->cg_p1, h->red};
     unsigned *ctr = h->ctr;
     Control *ctl = h->ctl;
     unsigned long long *ci = h->iscal;
-    void *args[] = {&in, &out, &npts, &count, &g, &s, &tol, &maxit, &wk, &wk2, &ctr, &ctl, &ci};
-    const void *fn = P.dim == 3 ? (const void *)k_coarse_cg_batch<3> : (const void *)k_coarse_cg_batch<2>;
-    if ((rc = coop_launch(h, fn, h->sweep_grid, SWEEP_BLOCK, args))) return rc;
+    void *args[] = {&in, &out, &npts, &count, &g, &s, &tol, &maxit, &wk, &wk2, &wkp, &ctr, &ctl, &ci};
+    const void *fn = P.dim == 3 ? (const void *)k_coarse_cg_batch<3>
+                                : (P.pcg ? (const void *)k_coarse_cg_batch<2, true> : (const void *)k_coarse_cg_batch<2>);
+    if ((rc = coop_launch(h, fn, h->sweep_grid, sweep_threads(P.dim == 2 && P.pcg), args))) return rc;
     if ((rc = check_control(h))) return rc;
     unsigned long long its = 0;
     HIPCHK(hipMemcpy(&its, h->iscal, sizeof its, hipMemcpyDeviceToHost));
@@ -821,7 +838,7 @@ constexpr long long kStaticPts = 1ll << 20;          // largest state: 2^20 poin
 constexpr long long kStaticRed = 2 * 4096;           // reduction slots (doubles)
 constexpr long long kStaticCtr = 4096 / 2;           // team counters: 4096 words
 constexpr long long kStaticCtl = 8;                  // Control + iteration counter
-constexpr long long kStaticDoubles = 4 * kStaticPts + kStaticRed + kStaticCtr + kStaticCtl;
+constexpr long long kStaticDoubles = 8 * kStaticPts + kStaticRed + kStaticCtr + kStaticCtl;
 static __device__ __align__(256) double scratch[kStaticDoubles];
 
 static std::mutex g_static_mu;
@@ -844,7 +861,10 @@ static int static_scratch(int device, double **ptr, int *grid) {
         int o2 = 0, o3 = 0;
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, (const void *)k_coarse_cg_batch<2>, SWEEP_BLOCK, 0));
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o3, (const void *)k_coarse_cg_batch<3>, SWEEP_BLOCK, 0));
-        if (std::min(o2, o3) < 1) return fail(PR_ENORESIDENT, "coarse solver kernel cannot be resident");
+        int op = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&op, (const void *)k_coarse_cg_batch<2, true>, PCG_THREADS,
+                                                            0));
+        if (std::min({o2, o3, op}) < 1) return fail(PR_ENORESIDENT, "coarse solver kernel cannot be resident");
         g_static_grid[device] = prop.multiProcessorCount;
         g_static_ptr[device] = (double *)p;
     }
@@ -877,7 +897,9 @@ extern "C" int pr_apply_coarse_static(const pr_config *cfg, int device, void *st
     if (count == 0) return PR_OK;
     hipStream_t st = (hipStream_t)stream;
     double *r0 = base, *r1 = base + kStaticPts, *p0 = base + 2 * kStaticPts, *p1 = base + 3 * kStaticPts;
-    double *red = base + 4 * kStaticPts;
+    double *w0 = base + 4 * kStaticPts, *w1 = base + 5 * kStaticPts, *s0 = base + 6 * kStaticPts,
+           *s1 = base + 7 * kStaticPts;
+    double *red = base + 8 * kStaticPts;
     unsigned *ctr = (unsigned *)(red + kStaticRed);
     Control *ctl = (Control *)(red + kStaticRed + kStaticCtr);
     unsigned long long *ci = (unsigned long long *)(red + kStaticRed + kStaticCtr + 2);
@@ -894,9 +916,11 @@ extern "C" int pr_apply_coarse_static(const pr_config *cfg, int device, void *st
     int maxit = P.cg_maxit;
     CGWork wk{r0, p0, p1, red};
     CGWork2 wk2{{r0, r1}, {p0, p1}, red};
-    void *args[] = {&in, &out, &npts, &count, &g, &s, &tol, &maxit, &wk, &wk2, &ctr, &ctl, &ci};
-    const void *fn = P.dim == 3 ? (const void *)k_coarse_cg_batch<3> : (const void *)k_coarse_cg_batch<2>;
-    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(SWEEP_BLOCK), args, 0, st);
+    CGWorkP wkp{{r0, r1}, {w0, w1}, {s0, s1}, p0, p1, red};
+    void *args[] = {&in, &out, &npts, &count, &g, &s, &tol, &maxit, &wk, &wk2, &wkp, &ctr, &ctl, &ci};
+    const void *fn = P.dim == 3 ? (const void *)k_coarse_cg_batch<3>
+                                : (P.pcg ? (const void *)k_coarse_cg_batch<2, true> : (const void *)k_coarse_cg_batch<2>);
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(sweep_threads(P.dim == 2 && P.pcg)), args, 0, st);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(PR_ENORESIDENT, "cooperative launch of %d workgroups failed: %s", grid, hipGetErrorString(e));

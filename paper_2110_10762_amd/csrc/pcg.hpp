@@ -1,0 +1,286 @@
+// Coarse propagator G in 2D by preconditioned conjugate gradients: the
+// backward-Euler system (I - s h^2 L_h) x = b (Section 3.1; backward Euler as
+// G, Section 5.1) solved by CG with a fixed polynomial preconditioner.
+//
+// Preconditioner: M^-1 = p(A), the degree-PD polynomial that PD steps of
+// Chebyshev acceleration on A z = r from z = 0 produce (Saad, Iterative
+// Methods for Sparse Linear Systems, Chebyshev acceleration): with the
+// spectrum of A = I - s h^2 L_h inside [1, 1 + 4 d s] (d = 2),
+//     1 - lambda p(lambda) = T_{PD+1}((theta - lambda)/delta) / T_{PD+1}(theta/delta),
+// theta, delta the centre and half-width of the interval.  p is positive on
+// the interval, so M^-1 is symmetric positive definite and CG applies; the
+// condition number drops from about 1 + 8 s (132 for the 1024^2 workload) to
+// about 6 (PD = 4), and the iteration count by 4-5x.  Applying p costs PD
+// stencil passes with no inner product: it needs no synchronisation.
+//
+// Iteration (Chronopoulos-Gear form of preconditioned CG: one team barrier
+// per iteration, the three inner products reduced together), with
+// u = M^-1 r, w = A u, s = A p kept as vectors:
+//     p_i = u_i + beta_i p_{i-1},   s_i = w_i + beta_i s_{i-1}
+//     x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i
+//     u_{i+1} = p(A) r_{i+1},       w_{i+1} = A u_{i+1}
+//     gamma = (r_{i+1}, u_{i+1}), delta = (w_{i+1}, u_{i+1}), rho = (r_{i+1}, r_{i+1})
+//     beta_{i+1} = gamma_{i+1} / gamma_i
+//     alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1} / alpha_i)
+// Start and stop as the unpreconditioned solvers: x0 = b and
+// ||r||_2 <= tol ||b||_2 (or x0 = 0 and ||r||_2^2 <= abs_thresh2 for the
+// increment form), rho being the true recurrence residual of CG.
+//
+// One sweep does a whole iteration.  A wave takes a strip of 64 columns and
+// a segment of rows and marches down it: each input row brings r_i, w_i and
+// s_{i-1}, from which s_i and r_{i+1} are formed at once; the PD Chebyshev
+// levels and the level forming w = A u each lag one row behind the one
+// before (two rows of the stencil operand and one row of the pointwise terms
+// held per level), so the output row is H = PD + 1 rows behind the input.
+// The strip's outer H columns and the segment's H halo rows on either side
+// are recomputed, not exchanged.  Out-of-domain rows and columns are read
+// from the odd extension of each vector, which every step commutes with, so
+// the zero Dirichlet values need no masks (as in the fine kernels).
+// HBM traffic per point and iteration: r, w, s, x, u, p read, the same six
+// written (96 B); the halo re-reads hit the caches.
+#pragma once
+#include "fine.hpp"
+#include "coarse.hpp"
+
+namespace pr {
+
+// Chebyshev polynomial degree of the preconditioner, and the shortest row
+// segment a wave of the marching sweep takes (the H = degree + 1 halo rows on
+// either side of a segment are recomputed).
+constexpr int PCG_DEGREE = 4;
+constexpr int PCG_MINSEG_GPU = 16;    // a team spanning the GPU (many waves per state)
+constexpr int PCG_MINSEG_TEAM = 24;   // teams of a few XCDs or less
+
+struct CGWorkP {
+    double *r[2], *w[2], *s[2];   // [npts] each, read with halos: double-buffered
+    double *u, *p;                // [npts] each, read and written only at the point: in place
+    double *red;                  // [8 * team size] reduction slots
+};
+
+// Chebyshev acceleration coefficients on [lo, hi]: level j (1..PD) forms
+//   R_j = R_{j-1} - A d_{j-1},  d_j = c1[j-1] d_{j-1} + c2[j-1] R_j,  X_{j+1} = X_j + d_j
+// from R_0 = r, d_0 = X_1 = r / theta; p(A) r = X_{PD+1}.
+template <int PD>
+struct Cheb {
+    double inv_theta;
+    double c1[PD], c2[PD];
+};
+
+template <int PD>
+__device__ __forceinline__ Cheb<PD> cheb_coef(double lo, double hi) {
+    Cheb<PD> c;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+    const double sigma = theta / delta;
+    c.inv_theta = 1.0 / theta;
+    double rho = 1.0 / sigma;
+#pragma unroll
+    for (int k = 0; k < PD; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        c.c1[k] = rn * rho;
+        c.c2[k] = 2.0 * rn / delta;
+        rho = rn;
+    }
+    return c;
+}
+
+// Set-up: x0 (b or 0), r0 = b - A x0 and the partial sum of (b, b), chunk by
+// chunk over the team's chunk range.
+__device__ __forceinline__ void cgp_start(const Geom &g, const ChunkRange &cr, double s, bool from_zero,
+                                          const double *__restrict__ b, double *__restrict__ x,
+                                          double *__restrict__ r0, double &bb) {
+    for (long long c = cr.begin + wave_id(); c < cr.end; c += nwaves()) {
+        const CPt q = cpt_at(g, c);
+        double v[4];
+        cpt_load<2>(q, g.n, [&](int j) { return b[j]; }, v);
+        double bc;
+        const double ab = cpt_apply<2>(q, v, bc, 4.0, s);
+        if (q.m & CP_VALID) {
+            x[q.c] = from_zero ? 0.0 : bc;
+            r0[q.c] = from_zero ? bc : bc - ab;
+            bb = __builtin_fma(bc, bc, bb);
+        }
+    }
+}
+
+// Raw loads of one march step: input row (r, w, s) and output row (x, u, p).
+struct PRow {
+    double r, w, s, x, u, p;
+};
+
+// One iteration (or, SETUP, the first preconditioning u0 = p(A) r0, w0 = A u0)
+// of the team's share of the state; accumulates the partial sums of
+// (r', u'), (w', u') and (r', r') over the points the wave owns.
+template <int PD, int PF, bool SETUP>
+__device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int minseg, double s,
+                                          const Cheb<PD> &cc, double alpha, double beta, bool first,
+                                          const double *__restrict__ rin, const double *__restrict__ win,
+                                          const double *__restrict__ sinp, double *__restrict__ rout,
+                                          double *__restrict__ wout, double *__restrict__ sout,
+                                          double *__restrict__ x, double *__restrict__ u,
+                                          double *__restrict__ p, double &ga, double &de, double &rr) {
+    constexpr int H = PD + 1;            // stencil levels between input and output row
+    constexpr int W = WAVE - 2 * H;      // columns a strip owns
+    const int n = g.n;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int waves = size * nwaves();
+    const int wid = rank * nwaves() + wave_id();
+    const int nsx = (n + W - 1) / W;
+    // segments of rows: about one (strip, segment) unit per wave, at least minseg rows
+    const int per = (int)(((long long)n * nsx + waves - 1) / waves);
+    const int seg = max(minseg, per);
+    const int nseg = (n + seg - 1) / seg;
+    const int units = nsx * nseg;
+    for (int un = wid; un < units; un += waves) {
+        const int sx = un % nsx;   // strips of the same rows side by side
+        const int ya = (un / nsx) * seg;
+        const int yb = min(n, ya + seg);
+        const int xcol = sx * W - H + lane;
+        double xsg;
+        const int xi = reflect(xcol, n, xsg);
+        const bool own = lane >= H && lane < H + W && xcol < n;
+        double w0[PD], w1[PD], Rd[PD], Xd[PD];
+#pragma unroll
+        for (int j = 0; j < PD; ++j) w0[j] = w1[j] = Rd[j] = Xd[j] = 0.0;
+        double ua = 0.0, ub = 0.0;
+        double DR[H], DS[H];   // r_{i+1} and s_i of the last H input rows, oldest first
+#pragma unroll
+        for (int j = 0; j < H; ++j) DR[j] = DS[j] = 0.0;
+        const int nrows = yb - ya + 2 * H;
+        const int k0 = ya - H;
+        PRow ring[PF];
+        double rsg[PF];
+        // Loads of march step kk into a ring slot: input row kk (odd extension)
+        // and output row kk - H (clamped into the segment when outside it, so
+        // every load is issued unconditionally); row addresses are scalar, the
+        // lane offset is 32-bit.
+        auto issue = [&](int kk, PRow &w, double &sg) {
+            double ys;
+            const int yi = reflect_row(kk, n, ys);
+            const long long rb = (long long)yi * n;
+            w.r = (rin + rb)[xi];
+            if constexpr (!SETUP) {
+                w.w = (win + rb)[xi];
+                w.s = first ? 0.0 : (sinp + rb)[xi];
+                const int y = min(max(kk - H, ya), yb - 1);
+                const long long ob = (long long)y * n;
+                w.x = (x + ob)[xi];
+                w.u = (u + ob)[xi];
+                w.p = first ? 0.0 : (p + ob)[xi];
+            }
+            sg = ys * xsg;
+        };
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            ring[q] = PRow{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            rsg[q] = 0.0;
+            if (q < nrows) issue(k0 + q, ring[q], rsg[q]);
+        }
+        for (int tb = 0; tb < nrows; tb += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int t = tb + q;
+                if (t >= nrows) break;
+                const int k = k0 + t;
+                const double sg = rsg[q];
+                // input row k: s_i and r_{i+1} (set-up: r0)
+                double rn, sn = 0.0;
+                if constexpr (SETUP) {
+                    rn = sg * ring[q].r;
+                } else {
+                    sn = __builtin_fma(beta, sg * ring[q].s, sg * ring[q].w);
+                    rn = __builtin_fma(-alpha, sn, sg * ring[q].r);
+                }
+                const double rf = DR[0], sf = DS[0];   // row k - H
+#pragma unroll
+                for (int j = 0; j + 1 < H; ++j) {
+                    DR[j] = DR[j + 1];
+                    DS[j] = DS[j + 1];
+                }
+                DR[H - 1] = rn;
+                DS[H - 1] = sn;
+                // Chebyshev levels: level j+1 forms row k-1-j from rows k-2-j..k-j of level j
+                double dn = rn * cc.inv_theta, Rn = rn, Xn = dn;
+#pragma unroll
+                for (int j = 0; j < PD; ++j) {
+                    const double l = from_lower_lane(w1[j]), r = from_upper_lane(w1[j]);
+                    const double ad = be_point(w1[j], (w0[j] + dn) + (l + r), 4.0, s);
+                    const double Rj = Rd[j] - ad;
+                    const double dj = __builtin_fma(cc.c2[j], Rj, cc.c1[j] * w1[j]);
+                    const double Xj = Xd[j] + dj;
+                    w0[j] = w1[j];
+                    w1[j] = dn;
+                    Rd[j] = Rn;
+                    Xd[j] = Xn;
+                    dn = dj;
+                    Rn = Rj;
+                    Xn = Xj;
+                }
+                // u = p(A) r' reached row k - PD; w = A u at row k - H
+                const double l = from_lower_lane(ub), r = from_upper_lane(ub);
+                const double wn = be_point(ub, (ua + Xn) + (l + r), 4.0, s);
+                const double un = ub;
+                ua = ub;
+                ub = Xn;
+                const int y = k - H;
+                if (y >= ya && y < yb && own) {
+                    const long long i = (long long)y * n + xcol;
+                    if constexpr (!SETUP) {
+                        const double pi = __builtin_fma(beta, ring[q].p, ring[q].u);
+                        x[i] = __builtin_fma(alpha, pi, ring[q].x);
+                        p[i] = pi;
+                        sout[i] = sf;
+                        rout[i] = rf;
+                    }
+                    u[i] = un;
+                    wout[i] = wn;
+                    ga = __builtin_fma(rf, un, ga);
+                    de = __builtin_fma(wn, un, de);
+                    rr = __builtin_fma(rf, rf, rr);
+                }
+                if (t + PF < nrows) issue(k + PF, ring[q], rsg[q]);
+            }
+        }
+    }
+}
+
+// Solves (I - s h^2 L_h) x = b in 2D by the preconditioned CG above; same
+// start and stop rules as cg_team_dim (abs_thresh2 < 0: x0 = b, relative
+// stop; >= 0: x0 = 0, absolute stop).  Returns the iteration count, or -1 if
+// the launch was aborted.  x must not alias b or the work vectors.
+template <int PD, int MINSEG, int PF = 4>
+__device__ int cg_team_2d_p(Team &tm, const Geom &g, double s, double tol, int maxit,
+                            const double *__restrict__ b, double *__restrict__ x, const CGWorkP &wk,
+                            double abs_thresh2) {
+    const bool from_zero = abs_thresh2 >= 0.0;
+    const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
+    // the spectrum of I - s h^2 L_h lies in (1, 1 + 8 s)
+    const Cheb<PD> cc = cheb_coef<PD>(1.0, 1.0 + 8.0 * s);
+    double bb = 0.0;
+    cgp_start(g, cr, s, from_zero, b, x, wk.r[0], bb);
+    if (!team_sync(tm)) return -1;
+    double part[4] = {0.0, 0.0, 0.0, bb}, tot[4];
+    cgp_sweep<PD, PF, true>(g, tm.rank, tm.size, MINSEG, s, cc, 0.0, 0.0, true, wk.r[0], nullptr, nullptr,
+                            nullptr, wk.w[0], nullptr, x, wk.u, wk.p, part[0], part[1], part[2]);
+    if (!team_reduce_n<4>(tm, part, wk.red, tot)) return -1;
+    double gamma = tot[0], rho = tot[2];
+    const double thresh = from_zero ? (abs_thresh2 > 0.0 ? abs_thresh2 : tol * tol * tot[3]) : tol * tol * tot[3];
+    double alpha = gamma / tot[1], beta = 0.0;
+    int cur = 0;
+    int it = 0;
+    while (it < maxit && rho > thresh) {
+        double pp[3] = {0.0, 0.0, 0.0}, tt[3];
+        cgp_sweep<PD, PF, false>(g, tm.rank, tm.size, MINSEG, s, cc, alpha, beta, it == 0, wk.r[cur], wk.w[cur],
+                                 wk.s[cur], wk.r[cur ^ 1], wk.w[cur ^ 1], wk.s[cur ^ 1], x, wk.u, wk.p, pp[0],
+                                 pp[1], pp[2]);
+        if (!team_reduce_n<3>(tm, pp, wk.red, tt)) return -1;
+        ++it;
+        beta = tt[0] / gamma;
+        alpha = tt[0] / (tt[1] - beta * tt[0] / alpha);
+        gamma = tt[0];
+        rho = tt[2];
+        cur ^= 1;
+    }
+    return it;
+}
+
+}  // namespace pr

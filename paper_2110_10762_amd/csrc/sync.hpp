@@ -15,6 +15,7 @@
 // the same kernels in "init" mode.
 #pragma once
 #include "coarse.hpp"
+#include "pcg.hpp"
 
 namespace pr {
 
@@ -41,6 +42,7 @@ struct SweepArgs {
     int cg_maxit;
     CGWork wk;
     CGWork2 wk2;        // 2D: one-synchronisation CG, products recomputed
+    CGWorkP wkp;        // 2D: preconditioned CG
     unsigned *ctr;
     Control *ctl;
 };
@@ -141,6 +143,13 @@ __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double
     return cg_team_2d_r<true>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
 
+template <int DIM>
+__device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
+                                       const double *b, double *x, const CGWorkP &wk, double abs_thresh2) {
+    static_assert(DIM == 2, "the preconditioned CG is two-dimensional");
+    return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_GPU>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+}
+
 template <int DIM, typename WK>
 __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol, int maxit, long long npts,
                                   int i0, int i1, int kguard, bool init, bool incr, const SweepBufs &B,
@@ -205,8 +214,14 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
 // chunk (1.16 s for the 1024^2, 64-slice sync solve; 1024 threads spill at
 // 128 registers, 1.53 s, and 512 threads take 1.26 s)
 constexpr int SWEEP_THREADS = 768;
-template <int DIM>
-__global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_cg(SweepArgs a) {
+// the preconditioned 2D CG holds its Chebyshev levels, row delay lines and
+// four rows of loads in flight in registers: 512 threads (256 registers per lane)
+constexpr int PCG_THREADS = 512;
+__host__ __device__ constexpr int sweep_threads(bool pcg) { return pcg ? PCG_THREADS : SWEEP_THREADS; }
+// PCG: 2D coarse solves by the preconditioned CG (pcg.hpp); otherwise the
+// unpreconditioned one-synchronisation CG.
+template <int DIM, bool PCG = false>
+__global__ __launch_bounds__(sweep_threads(PCG)) void k_sweep_cg(SweepArgs a) {
     Team tm{a.ctr, a.ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
     if (!team_setup(tm, true)) return;
     __shared__ double lds[MAX_WAVES];
@@ -214,7 +229,10 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_cg(SweepArgs a) {
     unsigned long long its = 0;
     const SweepBufs B{a.lam, a.v, a.w, a.wn, a.d0, a.d1};
     bool ok;
-    if constexpr (DIM == 2)
+    if constexpr (DIM == 2 && PCG)
+        ok = team_coarse_sweep<2>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
+                                  a.incr != 0, B, a.wkp, dmax, its, lds);
+    else if constexpr (DIM == 2)
         ok = team_coarse_sweep<2>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
                                   a.incr != 0, B, a.wk2, dmax, its, lds);
     else
@@ -233,17 +251,20 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_cg(SweepArgs a) {
 // state c of the batch is solved by the whole grid, one after the other,
 // with the solver of the synchronous sweep (2D: the one-synchronisation CG;
 // 3D: the marching two-phase CG).
-template <int DIM>
-__global__ __launch_bounds__(SWEEP_THREADS) void k_coarse_cg_batch(const double *src, double *dst, long long npts,
+template <int DIM, bool PCG = false>
+__global__ __launch_bounds__(sweep_threads(PCG)) void k_coarse_cg_batch(const double *src, double *dst, long long npts,
                                                            int count, Geom g, double s, double tol,
-                                                           int maxit, CGWork wk, CGWork2 wk2, unsigned *ctr,
-                                                           Control *ctl, unsigned long long *cg_iters) {
+                                                           int maxit, CGWork wk, CGWork2 wk2, CGWorkP wkp,
+                                                           unsigned *ctr, Control *ctl,
+                                                           unsigned long long *cg_iters) {
     Team tm{ctr, ctl, (int)gridDim.x, (int)blockIdx.x, 0u};
     if (!team_setup(tm, true)) return;
     unsigned long long its = 0;
     for (int c = 0; c < count; ++c) {
         int it;
-        if constexpr (DIM == 2)
+        if constexpr (DIM == 2 && PCG)
+            it = team_cg<2>(tm, g, s, tol, maxit, src + c * npts, dst + c * npts, wkp, -1.0);
+        else if constexpr (DIM == 2)
             it = team_cg<2>(tm, g, s, tol, maxit, src + c * npts, dst + c * npts, wk2, -1.0);
         else
             it = team_cg<3>(tm, g, s, tol, maxit, src + c * npts, dst + c * npts, wk, -1.0);

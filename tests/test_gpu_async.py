@@ -46,10 +46,12 @@ def schedule_rows(events, N, L):
     return tab.ravel().tolist()
 
 
-def solve(p, mode, schedule=None, L=0, teams=0, delays=None, eps=None, latency_us=0.0, **over):
+def solve(p, mode, schedule=None, L=0, teams=0, delays=None, eps=None, latency_us=0.0, drop_every=None,
+          reset_after=None, **over):
     prob = pr.Problem(pr.config_of(p, eps=p.eps if eps is None else eps, **over))
     prob.set_async_options(mode=mode, teams=teams, max_local_iters=L, schedule=schedule,
-                           delay_spins=delays, time_limit_s=30.0, latency_us=latency_us)
+                           delay_spins=delays, time_limit_s=30.0, latency_us=latency_us,
+                           drop_every=drop_every, reset_after=reset_after)
     lam = torch.empty((p.nslices + 1,) + p.u0.shape, dtype=torch.float64, device=DEV)
     st = pr.Stats(p.nslices)
     prob.solve_async(dev(p.u0), lam, st, allow_notconv=True)
@@ -299,3 +301,68 @@ def test_free_mode_ring_reuse_under_uneven_speeds_2d():
     prob, lam, st = solve(p, pr.PR_ASYNC_FREE, teams=12, delays=delays)
     assert st.converged == 1
     assert rel(lam, heat.serial_fine(p.u0, d.r, d.m, d.nslices)) <= TOL
+
+
+# ------------------------------------------------------------------ failure injection
+
+@pytest.mark.parametrize("which", ["1d", "2d"])
+def test_lost_publications_free_and_exact(which):
+    # some updates are computed but never published (lost messages): the
+    # successors keep reading older versions.  Every slice still updates
+    # infinitely often (Section 2.1), so FREE reaches the fixed point and
+    # EXACT the serial fine solution bit for bit (finite termination)
+    p = workloads.heat1d() if which == "1d" else workloads.heat2d(n=80, nslices=8, T=1e-2)
+    d = disc_of(p)
+    drops = [(2 + i % 3) if i % 2 == 0 else 0 for i in range(p.nslices)]
+    prob = pr.Problem(pr.config_of(p))
+    ser = torch.empty((p.nslices + 1,) + p.u0.shape, dtype=torch.float64, device=DEV)
+    prob.solve_fine(dev(p.u0), ser)
+    ser = ser.cpu().numpy()
+    star = heat.serial_fine(p.u0, d.r, d.m, d.nslices)
+    for mode in (pr.PR_ASYNC_FREE, pr.PR_ASYNC_EXACT):
+        # lost versions slow the information down the chain: room for more
+        # local iterations than the default cap
+        prob.set_async_options(mode=mode, time_limit_s=30.0, drop_every=drops, max_local_iters=12 * p.nslices + 40)
+        lam = torch.empty_like(dev(ser))
+        st = pr.Stats(p.nslices)
+        prob.solve_async(dev(p.u0), lam, st, allow_notconv=True)
+        got = lam.cpu().numpy()
+        print(f"{which} mode {mode}: kappa={st.kappa} k_i={st.k_per_slice}", flush=True)
+        assert st.converged == 1
+        if mode == pr.PR_ASYNC_EXACT:
+            assert np.array_equal(got, ser)
+        else:
+            assert rel(got, star) <= TOL
+
+
+@pytest.mark.parametrize("which", ["1d", "2d"])
+def test_slice_resets_free(which):
+    # slices lose their state mid-run and start again from the initial guess
+    # (the oracle's AsyncReplay.reset, pinned there to still reach the fixed
+    # point); the free-running iteration recovers and stops within the bar
+    p = workloads.heat1d() if which == "1d" else workloads.heat2d(n=80, nslices=8, T=1e-2)
+    d = disc_of(p)
+    resets = [-1] * p.nslices
+    resets[2] = 3
+    resets[p.nslices - 2] = 5
+    resets[p.nslices - 1] = 1
+    _, lam, st = solve(p, pr.PR_ASYNC_FREE, reset_after=resets, drop_every=[0, 3] * (p.nslices // 2),
+                       L=12 * p.nslices + 40)
+    print(f"{which}: kappa={st.kappa} k_i={st.k_per_slice}", flush=True)
+    assert st.converged == 1
+    assert rel(lam, heat.serial_fine(p.u0, d.r, d.m, d.nslices)) <= TOL
+    assert st.k_per_slice[p.nslices - 1] >= 2
+
+
+def test_failure_injection_rejected_where_unsupported():
+    p = workloads.heat1d()
+    prob = pr.Problem(pr.config_of(p))
+    N = p.nslices
+    with pytest.raises(pr.PRError):
+        prob.set_async_options(mode=pr.PR_ASYNC_EXACT, reset_after=[1] * N)
+    with pytest.raises(pr.PRError):
+        prob.set_async_options(mode=pr.PR_ASYNC_PIPELINED, drop_every=[2] * N)
+    with pytest.raises(pr.PRError):
+        prob.set_async_options(mode=pr.PR_ASYNC_FREE, drop_every=[1] * N)
+    with pytest.raises(ValueError):
+        prob.set_async_options(mode=pr.PR_ASYNC_FREE, drop_every=[2] * (N - 1))

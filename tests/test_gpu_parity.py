@@ -52,7 +52,9 @@ def test_fine_1d(n, steps):
         assert rel(got[c], heat.fine(x[c], r, steps)) <= 1e-12
 
 
-@pytest.mark.parametrize("n", [63, 100, 1, 300])
+# n >= 64 XP: strips flush with both boundaries (one strip at n = 128 for
+# XP = 2, two up to 240, then interior strips); smaller n: odd extension
+@pytest.mark.parametrize("n", [63, 100, 1, 128, 129, 240, 241, 300])
 def test_fine_2d_all_shapes_bitwise_and_vs_oracle(n):
     rng = np.random.default_rng(7 + n)
     cnt = 3
@@ -143,6 +145,54 @@ def test_coarse_cg(dim, n):
     assert its > 0
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 10, 53, 54, 55, 64, 65, 108, 109, 130])
+def test_coarse_pcg_vs_plain_and_oracle(n):
+    # the preconditioned CG (default in 2D) on ragged grids: strip borders at
+    # multiples of 54 columns, segments of 16 rows, a grid smaller than the
+    # halo (n <= 5); against the oracle's textbook CG, the exact G and the
+    # unpreconditioned GPU solver
+    rng = np.random.default_rng(4000 + n)
+    x = states(rng, 2, (n, n))
+    cfg = dict(dim=2, n=n, nu=1.0, T=1e-3, nslices=4, dt_nominal=0.1 / (n + 1) ** 2)
+    pcg = pr.Problem(pr.make_config(**cfg))
+    plain = pr.Problem(pr.make_config(**cfg, cg_precond=-1))
+    s = pcg.info().s
+    y = torch.empty_like(dev(x))
+    y0 = torch.empty_like(dev(x))
+    its = pcg.apply_coarse(dev(x), y, 2)
+    its0 = plain.apply_coarse(dev(x), y0, 2)
+    got, got0 = y.cpu().numpy(), y0.cpu().numpy()
+    for c in range(2):
+        want, _ = heat.coarse_cg(x[c], s, 1e-12)
+        assert rel(got[c], want) <= TOL, c
+        assert rel(got[c], spectral.coarse(x[c], s)) <= TOL, c
+        assert rel(got[c], got0[c]) <= TOL, c
+    assert its <= its0
+
+
+def test_coarse_pcg_iterations_full_size():
+    # 1024^2, s = 16.4: the polynomial preconditioner cuts the CG iterations
+    # by more than 3x (condition number ~132 -> ~6)
+    p = workloads.heat2d()
+    d = disc_of(p)
+    x = dev(p.u0)
+    y = torch.empty_like(x)
+    y0 = torch.empty_like(x)
+    its = pr.Problem(pr.config_of(p)).apply_coarse(x, y, 1)
+    its0 = pr.Problem(pr.config_of(p, cg_precond=-1)).apply_coarse(x, y0, 1)
+    print(f"1024^2 coarse solve: {its} preconditioned vs {its0} plain CG iterations", flush=True)
+    assert 3 * its < its0
+    exact = spectral.coarse(p.u0, d.s)
+    assert rel(y.cpu().numpy(), exact) <= TOL
+    assert rel(y0.cpu().numpy(), exact) <= TOL
+
+
+def test_pcg_rejects_unsupported_degree():
+    with pytest.raises(pr.PRError) as e:
+        pr.Problem(pr.make_config(2, 16, 1.0, 1e-3, 4, 1e-5, cg_precond=3))
+    assert e.value.code == pr.PR_EINVAL
+
+
 # ------------------------------------------------------------------ synchronous Parareal
 
 def run_sync(p, eps=None, kmax=0, **over):
@@ -192,11 +242,12 @@ def test_sync_finite_termination_bitwise_gpu():
 
 # n = 70 and 130: two and three column strips of the coarse solver, the last
 # one ragged
+@pytest.mark.parametrize("precond", [0, -1])
 @pytest.mark.parametrize("n,N,T", [(31, 8, 2e-2), (70, 6, 5e-3), (130, 5, 5e-3)])
-def test_sync_2d_vs_oracle(n, N, T):
+def test_sync_2d_vs_oracle(n, N, T, precond):
     p = workloads.heat2d(n=n, nslices=N, T=T)
     d = disc_of(p)
-    _, lam, st = run_sync(p)
+    _, lam, st = run_sync(p, cg_precond=precond)
     props = heat.Propagators(d, cg_tol=p.cg_tol)
     ref = parareal.parareal_sync(p.u0, props.F, props.G, d.nslices, eps=p.eps)
     assert st.iters == ref.iters

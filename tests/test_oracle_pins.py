@@ -530,6 +530,41 @@ def test_async_drift_bounds_the_true_staleness(seed):
             assert true <= st.staleness(s) * (1 + 1e-12) + 1e-300
 
 
+@pytest.mark.parametrize("seed", [0, 3])
+def test_async_resets_still_reach_the_fixed_point(seed):
+    # slices that lose their state mid-run (start again from the initial
+    # guess) perturb the iteration once; the fair, bounded-delay schedule still
+    # reaches the serial fine solution bit for bit (finite termination), and
+    # the tolerance stop still lands within the bar
+    p = workloads.heat1d()
+    d = _disc(p)
+    pr = heat.Propagators(d)
+    star = heat.serial_fine(p.u0, d.r, d.m, d.nslices)
+    resets = {3: 4, 7: 9, 12: 15, 16: 2}
+    st = parareal.run_random(p.u0, pr.F, pr.G, d.nslices, seed=seed, max_delay=2, exact=True, resets=resets)
+    assert st.converged_exact()
+    assert np.array_equal(st.current(), star)
+    st2 = parareal.run_random(p.u0, pr.F, pr.G, d.nslices, seed=seed, max_delay=2, eps=p.eps, resets=resets)
+    assert st2.converged_tol(p.eps)
+    assert np.max(np.abs(st2.current() - star)) < 1e-10 * np.max(np.abs(star))
+
+
+def test_async_reset_restarts_from_the_initial_guess():
+    # after a reset the next update is exactly the first update of Algorithm 2
+    # with the newest predecessor as coarse input: F(lambda_{i-1}^0) +
+    # G(x_new) - lambda_i^0
+    p = workloads.heat1d()
+    d = _disc(p)
+    pr = heat.Propagators(d)
+    st = parareal.replay(p.u0, pr.F, pr.G, d.nslices, parareal.sync_schedule(d.nslices, 5))
+    st.reset(4)
+    assert st.final_from[4] == -1 and st.final_from[9] == -1 and st.final_from[3] >= 0
+    j = st.newest(3)
+    st.step(4, j)
+    want = pr.F(st.versions[3][0]) + (pr.G(st.versions[3][j]) - st.versions[4][0])
+    assert np.array_equal(st.versions[4][-1], want)
+
+
 def test_async_contraction_when_alpha_below_one():
     u0, Fp, Gp, Fm, Gm, r, m = _tiny()
     N = 8
