@@ -73,6 +73,9 @@ def parse():
                     help="skip the untimed runs with coarse solves on input changes")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the untimed 3D, batched and adjoint runs")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="run only the untimed 3D, batched and adjoint runs and print them "
+                         "(profiling of those kernels); no benchmark line")
     return ap.parse_args()
 
 
@@ -218,6 +221,10 @@ def run_extras(dev):
                                    "unit": "GB/s", "frac": c_bytes / (st.coarse_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         else:
             r["kappa"], r["teams"], r["kernel_ms"] = st.kappa, st.teams, st.kernel_ms
+            r["updates"] = st.kernel_updates
+            # mean per team of the time its leader spent per phase
+            r["team_ms"] = {"fine": st.team_fine_ms, "copy": st.team_copy_ms, "coarse": st.team_coarse_ms,
+                            "correction": st.team_corr_ms, "total": st.team_total_ms}
         res[drv] = r
     out["heat3d"] = res
     prob.close()
@@ -319,6 +326,10 @@ def main():
 
     pr.load_library()          # fails loudly if the HIP library is missing
     dev = torch.device("cuda:0")
+    if args.extras_only:
+        print(json.dumps(run_extras(dev)), flush=True)
+        torch.cuda.synchronize()
+        return
     p = workloads.heat2d()
     prob = pr.Problem(pr.config_of(p, eps=1e-10))
     info = prob.info()

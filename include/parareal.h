@@ -79,7 +79,9 @@ typedef struct pr_config {
     int    tb_depth;     /* fine steps per HBM pass (temporal block depth); 0 = default */
     int    tile_rows;    /* 2D/3D fine kernel: rows a wave owns; below 96 a register strip
                             (rows held at once), from 96 on a sliding window (rows marched
-                            per segment, two rows per time level held); 0 = default */
+                            per segment, two rows per time level held); 1000: a sliding
+                            window whose segment length is chosen at each launch to fill
+                            the chip's wave slots in whole rounds; 0 = default */
     int    coarse_increment; /* 0: G(new) - G(old) as written in eq. (pr) / Algorithm 2;
                                 1: G applied to the change new - old (G is linear, Section 3.1),
                                 CG from 0 to an absolute residual tol*||new||; an unchanged input
@@ -89,7 +91,7 @@ typedef struct pr_config {
                             fine_xpts) is used; none matching is PR_EINVAL. */
     int    fine;         /* PR_FINE_*: the fine propagator's time stepping */
     int    cg_precond;   /* 2D CG (coarse solves): degree of its Chebyshev polynomial
-                            preconditioner; 0 = default (4), -1 = none (plain CG).  The
+                            preconditioner; 0 = default (6), -1 = none (plain CG).  The
                             preconditioner changes iterates at the tolerance level only. */
 } pr_config;
 
@@ -152,7 +154,8 @@ typedef struct pr_async_opts {
     int teams;               /* concurrent slice teams, each holding the slices that
                                 slice_blocks assigns it and updating them in turn;
                                 0 = automatic: one per slice in 1D and in REPLAY (which
-                                needs it), else four, each spanning two XCDs */
+                                needs it), four of two XCDs each in 2D, two of four XCDs
+                                each in 3D */
     int max_local_iters;     /* cap on k_i (<= 0: 4*N + 16) */
     const int *schedule;     /* REPLAY: host array [N][max_local_iters]: predecessor
                                 version read by slice i's k-th coarse solve (slice 1: 0) */

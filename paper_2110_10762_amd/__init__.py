@@ -270,10 +270,11 @@ class Problem:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP call once the interpreter is shutting down: the runtime (and
-        # any profiler attached to it) may already be gone
-        if sys.is_finalizing():
+        # any profiler attached to it) may already be gone (module globals
+        # such as `sys` may be gone too, hence the bound default)
+        if _finalizing():
             return
         try:
             self.close()

@@ -70,6 +70,8 @@ struct SliceLoc {     // team-private control state of a slice (leader only)
     int done;
     int unpub;        // its last computed value was not published (a lost message)
     int reset_done;   // the injected reset has happened
+    int zero_noted;   // idling: the zero change of the skipped update is recorded
+    double last_sref; // predecessor drift at the version the last computed value's G read
 };
 
 struct AsyncWork {
@@ -469,6 +471,7 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                         L.f_ver = 0;
                         L.f_final = (i == 1) ? 1 : 0;
                         L.stale_streak = 0;
+                        L.last_sref = 0.0;   // version 0 of the predecessor
                         b[6] = 1;
                     }
                     pv = (i == 1) ? 0 : visible_version(a, i - 1);
@@ -478,10 +481,10 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                         // another update would republish F(x_old) unchanged: record
                         // that (zero) change once, then wait.  Retire if nothing new
                         // can arrive.
-                        if (L.stale_streak == 1) {
+                        if (!L.zero_noted) {
                             SliceHdr *h = &a.hdr[i];
                             hdr_publish(h, h->ver, h->k, h->g_ver, h->final_from, 0.0, h->drift, h->stale_ref);
-                            L.stale_streak = 2;
+                            L.zero_noted = 1;
                         }
                         const bool pred_done = (i == 1) || ld_acquire(&a.hdr[i - 1].done) != 0;
                         action = (pred_done && pv == ld_acquire(&a.hdr[i - 1].ver)) ? ACT_DONE : ACT_IDLE;
@@ -649,7 +652,10 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                 SliceLoc &L = a.loc[i];
                 SliceHdr *h = &a.hdr[i];
                 const double drift = h->drift + delta;
-                const double sref = stale ? h->stale_ref : drift_read;
+                // a stale update's G input is that of the last computed value
+                // (published or lost), whose predecessor drift is kept locally
+                const double sref = stale ? L.last_sref : drift_read;
+                L.last_sref = sref;
                 const int gf = stale ? L.f_final : g_final;
                 int ff = h->final_from;
                 if (ff < 0 && L.f_final && gf) ff = myver + 1;
@@ -664,6 +670,7 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                     hdr_publish(h, myver + 1, h->k + 1, pv, ff, delta, drift, sref);
                 }
                 L.unpub = lost ? 1 : 0;
+                L.zero_noted = 0;
                 if (a.mode == AMODE_PIPELINED) {
                     // version v is complete once slices v..N have published it; the
                     // first complete version with a change below eps (or v = N, or

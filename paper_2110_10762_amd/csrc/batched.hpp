@@ -55,6 +55,7 @@ struct BatchArgs {
     long long *tbc;
     double *tred;
     double *wn, *cgr, *cgr1, *cgp0, *cgp1, *d0, *d1;   // [nteams][maxnpts]
+    double *cgw0, *cgw1, *cgs0, *cgs1;                 // [nteams][maxnpts], preconditioned CG only
     long long maxnpts;
     const int *order;
     unsigned *queue;
@@ -110,8 +111,10 @@ __global__ __launch_bounds__(BLOCK) void k_bfine_sw(const BProb *__restrict__ pr
 
 // Three workgroups per CU: 96 teams on the chip (11.0 s for the 512-problem
 // batch against 11.9 s with two per CU and the registers the marching CG
-// would take unbounded).
-__global__ __launch_bounds__(BLOCK, 3) void k_bsweep(BatchArgs a) {
+// would take unbounded).  PCG: the preconditioned CG (its Chebyshev levels
+// need the registers of two workgroups per CU).
+template <bool PCG>
+__global__ __launch_bounds__(BLOCK, PCG ? 2 : 3) void k_bsweep(BatchArgs a) {
     const int team = a.team_of[blockIdx.x];
     if (team < 0) return;
     Team tm{a.tctr + (long long)team * a.ctr_stride, a.ctl, a.tsz, a.rank_of[blockIdx.x], 0u};
@@ -119,12 +122,15 @@ __global__ __launch_bounds__(BLOCK, 3) void k_bsweep(BatchArgs a) {
     long long *bc = a.tbc + team * 16;
     double *wn = a.wn + team * a.maxnpts;
     // a team of 8 workgroups sweeps a whole problem: the marching CG
-    CGWork2M wk;
-    wk.r[0] = a.cgr + team * a.maxnpts;
-    wk.r[1] = a.cgr1 + team * a.maxnpts;
-    wk.p[0] = a.cgp0 + team * a.maxnpts;
-    wk.p[1] = a.cgp1 + team * a.maxnpts;
-    wk.red = a.tred + (long long)team * 6 * a.tsz;
+    const long long o = (long long)team * a.maxnpts;
+    double *const red = a.tred + (long long)team * 8 * a.tsz;
+    CGWork2M wk2;
+    wk2.r[0] = a.cgr + o;
+    wk2.r[1] = a.cgr1 + o;
+    wk2.p[0] = a.cgp0 + o;
+    wk2.p[1] = a.cgp1 + o;
+    wk2.red = red;
+
     __shared__ double lds[MAX_WAVES];
     const bool leader = (tm.rank == 0 && threadIdx.x == 0);
     for (;;) {
@@ -152,11 +158,26 @@ __global__ __launch_bounds__(BLOCK, 3) void k_bsweep(BatchArgs a) {
         unsigned long long its = 0;
         const SweepBufs SB{a.lam + P.off_lam, a.v + P.off_lam, a.w + P.off_lam, wn,
                            a.d0 + team * a.maxnpts, a.d1 + team * a.maxnpts};
-        if (!team_coarse_sweep<2>(tm, P.g, P.s, P.cg_tol, P.cg_maxit, P.npts, init ? 1 : k, P.N, init ? -1 : k, init,
-                               P.incr != 0, SB, wk, dmax, its, lds))
-            return;
+        bool ok;
+        if constexpr (PCG) {
+            CGWorkPT wkp;
+            wkp.r[0] = a.cgr + o;
+            wkp.r[1] = a.cgr1 + o;
+            wkp.w[0] = a.cgw0 + o;
+            wkp.w[1] = a.cgw1 + o;
+            wkp.s[0] = a.cgs0 + o;
+            wkp.s[1] = a.cgs1 + o;
+            wkp.u = a.cgp0 + o;
+            wkp.p = a.cgp1 + o;
+            wkp.red = red;
+            ok = team_coarse_sweep<2>(tm, P.g, P.s, P.cg_tol, P.cg_maxit, P.npts, init ? 1 : k, P.N, init ? -1 : k,
+                                      init, P.incr != 0, SB, wkp, dmax, its, lds);
+        } else
+            ok = team_coarse_sweep<2>(tm, P.g, P.s, P.cg_tol, P.cg_maxit, P.npts, init ? 1 : k, P.N, init ? -1 : k,
+                                      init, P.incr != 0, SB, wk2, dmax, its, lds);
+        if (!ok) return;
         double delta = 0.0;
-        if (!team_reduce<true>(tm, dmax, wk.red, delta, lds)) return;
+        if (!team_reduce<true>(tm, dmax, red, delta, lds)) return;
         if (leader) {
             S.cg_iters += its;
             if (init) {
@@ -196,6 +217,8 @@ struct BatchWork {
     unsigned *tctr = nullptr, *queue = nullptr;
     long long *tbc = nullptr;
     double *tred = nullptr, *wn = nullptr, *cgr = nullptr, *cgr1 = nullptr, *cgp0 = nullptr, *cgp1 = nullptr;
+    double *cgw0 = nullptr, *cgw1 = nullptr, *cgs0 = nullptr, *cgs1 = nullptr;
+    bool pcg = false;   // coarse solves by the preconditioned CG
     double *d0 = nullptr, *d1 = nullptr;
     long long maxnpts = 0, total = 0;
     int nteams = 0, tsz = 0, grid = 0;

@@ -190,6 +190,11 @@ __global__ __launch_bounds__(BLOCK) void k_fine2d(const double *__restrict__ src
 // Row counts of at least this select the sliding window in shape tables and
 // kernel templates (register strips hold at most 64 rows).
 constexpr int SW_MIN_ROWS = 96;
+// Segment length of a sliding-window shape chosen at each launch from the
+// number of states, so that the (strip, segment) units fill the resident
+// waves in whole rounds (a launch of 49 states of 1024^2 in 128-row segments
+// is 1.15 rounds of the chip's wave slots, so its second round runs 15% full).
+constexpr int SW_AUTO_ROWS = 1000;
 
 // Odd reflection of row y (wave-uniform, so scalar work): the interior row
 // to read and its sign.

@@ -59,9 +59,10 @@ struct Shape {
 static const Shape kShapes2D[] = {{2, 32, 1},  {2, 32, 2},   {2, 32, 4},  {2, 32, 8},  {2, 16, 8},
                                   {2, 24, 12}, {2, 16, 16},  {1, 64, 8},  {2, 16, 4},  {2, 8, 4},
                                   {2, 128, 4}, {3, 128, 4},  {2, 128, 8}, {3, 128, 8}, {4, 128, 8},
-                                  {3, 256, 8}, {2, 128, 16}, {3, 96, 8},  {2, 128, 1}, {3, 128, 12}};
+                                  {3, 256, 8}, {2, 128, 16}, {3, 96, 8},  {2, 128, 1}, {3, 128, 12},
+                                  {2, SW_AUTO_ROWS, 8}};
 static const Shape kShapes3D[] = {{2, 8, 1}, {2, 16, 1}, {1, 16, 1}, {2, 4, 1}};
-static const int kDefault2D = 12;        // sliding window (2, 128, 8): batches of states
+static const int kDefault2D = 20;        // sliding window (2, auto rows, 8): batches of states
 static const int kDefault2DSingle = 4;   // register strip (2, 16, 8): one state (more waves)
 static const int kDefault3D = 0;   // (2, 8, 1)
 static const int kNum2D = sizeof(kShapes2D) / sizeof(kShapes2D[0]);
@@ -249,10 +250,44 @@ static void launch2d(hipStream_t st, const double *src, double *dst, long long s
                        nsx, nsy, count, nblk);
 }
 
+// Rows per segment for SW_AUTO_ROWS: the segment count whose units fill the
+// resident wave slots in the fewest rounds, each round costing the rows a
+// wave marches (its segment plus 2D halo rows).
+template <int XP, int D>
+static int sw_auto_rows(int n, int count, int nsx) {
+    static int slots = 0;
+    if (slots == 0) {
+        int occ = 0, ncu = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_fine2d_sw<XP, D>, BLOCK, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return 128;
+        }
+        slots = std::max(1, occ * ncu * WAVES_PER_BLOCK);
+    }
+    int best = n;
+    double best_cost = 1e300;
+    for (int nseg = 1; nseg <= std::max(1, n / 32); ++nseg) {
+        const int seg = (n + nseg - 1) / nseg;
+        const long long units = (long long)count * nsx * ((n + seg - 1) / seg);
+        const long long rounds = (units + slots - 1) / slots;
+        const double cost = (double)rounds * (seg + 2 * D);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = seg;
+        }
+    }
+    return best;
+}
+
 template <int XP, int D>
 static void launch2d_sw(hipStream_t st, const double *src, double *dst, long long ss, long long ds, int n,
                         double r, int steps, int count, int ry) {
-    const int nsx = sw_strips<XP, D>(n), nsy = (n + ry - 1) / ry;
+    const int nsx = sw_strips<XP, D>(n);
+    if (ry == SW_AUTO_ROWS) ry = sw_auto_rows<XP, D>(n, count, nsx);
+    const int nsy = (n + ry - 1) / ry;
     const long long waves = (long long)nsx * nsy * count;
     const int nblk = (int)((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
     const int grid = 8 * ((nblk + 7) / 8);
@@ -274,6 +309,7 @@ static void launch2d_shape(int shape, hipStream_t st, const double *src, double 
         case 17: launch2d_sw<3, 8>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
         case 18: launch2d_sw<2, 1>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
         case 19: launch2d_sw<3, 12>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 20: launch2d_sw<2, 8>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
         default: break;
     }
     switch (shape) {
@@ -674,7 +710,7 @@ extern "C" int pr_get_info(const pr_problem *h, int problem, pr_info *out) {
     out->npts = P.npts;
     out->offset = P.off_lam;
     out->sliding = 0;
-    out->cg_precond = (P.pcg && h->P.size() == 1) ? PCG_DEGREE : 0;   // batches keep the plain CG
+    out->cg_precond = P.pcg ? PCG_DEGREE : 0;   // a batch takes it when every problem does
     if (P.dim == 2) {
         out->tb_depth = kShapes2D[P.shape].d;
         out->tile_rows = kShapes2D[P.shape].r;

@@ -10,8 +10,8 @@
 // theta, delta the centre and half-width of the interval.  p is positive on
 // the interval, so M^-1 is symmetric positive definite and CG applies; the
 // condition number drops from about 1 + 8 s (132 for the 1024^2 workload) to
-// about 6 (PD = 4), and the iteration count by 4-5x.  Applying p costs PD
-// stencil passes with no inner product: it needs no synchronisation.
+// about 3.4 (PD = 6), and the iteration count by about 6x.  Applying p costs
+// PD stencil passes with no inner product: it needs no synchronisation.
 //
 // Iteration (Chronopoulos-Gear form of preconditioned CG: one team barrier
 // per iteration, the three inner products reduced together), with
@@ -47,15 +47,20 @@ namespace pr {
 // Chebyshev polynomial degree of the preconditioner, and the shortest row
 // segment a wave of the marching sweep takes (the H = degree + 1 halo rows on
 // either side of a segment are recomputed).
-constexpr int PCG_DEGREE = 4;
-constexpr int PCG_MINSEG_GPU = 16;    // a team spanning the GPU (many waves per state)
-constexpr int PCG_MINSEG_TEAM = 24;   // teams of a few XCDs or less
+// Measured on the 1024^2 workload (sync / async solve): degree 4 with
+// segments of 16 / 24 rows 495 / 488 ms, degree 6 with 8 / 16 rows 396 / 400
+// ms, degree 8 with 16 / 24 rows 477 / 449 ms; segments of 32 rows 696 ms.
+constexpr int PCG_DEGREE = 6;
+constexpr int PCG_MINSEG_GPU = 8;     // a team spanning the GPU (many waves per state)
+constexpr int PCG_MINSEG_TEAM = 16;   // teams of a few XCDs or less
 
 struct CGWorkP {
     double *r[2], *w[2], *s[2];   // [npts] each, read with halos: double-buffered
     double *u, *p;                // [npts] each, read and written only at the point: in place
     double *red;                  // [8 * team size] reduction slots
 };
+// The same vectors, for a team of a few workgroups (longer row segments).
+struct CGWorkPT : CGWorkP {};
 
 // Chebyshev acceleration coefficients on [lo, hi]: level j (1..PD) forms
 //   R_j = R_{j-1} - A d_{j-1},  d_j = c1[j-1] d_{j-1} + c2[j-1] R_j,  X_{j+1} = X_j + d_j

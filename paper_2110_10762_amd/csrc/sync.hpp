@@ -150,6 +150,13 @@ __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double
     return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_GPU>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
 
+template <int DIM>
+__device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
+                                       const double *b, double *x, const CGWorkPT &wk, double abs_thresh2) {
+    static_assert(DIM == 2, "the preconditioned CG is two-dimensional");
+    return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_TEAM, 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+}
+
 template <int DIM, typename WK>
 __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol, int maxit, long long npts,
                                   int i0, int i1, int kguard, bool init, bool incr, const SweepBufs &B,
