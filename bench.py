@@ -13,10 +13,12 @@ launches' own duration (device events around each launch); the whole step's
 rate (all fine updates of both solves over the wall time of the timed steps)
 is reported beside it.
 
-Untimed extras (outside the timed region, skipped with --no-extras): the 3D
-workload (256^3, 128 slices), the 512-problem batch (hipGraph, autotuned fine
-kernel) and the adjoint gradient (512^2, 32 slices), each checked against the
-oracle's exact modal forms at sampled outputs.
+Untimed extras (outside the timed region, skipped with --no-extras): the 2D
+fine sweep at every sliding-window depth D, the 3D workload (256^3, 128
+slices), the 512-problem batch (hipGraph, autotuned fine kernel) and the
+adjoint gradient (512^2, 32 slices), each compared at sampled outputs with the
+library's own serial fine integration (their agreement with the oracle is
+checked by the GPU tests).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
 """
@@ -169,7 +171,8 @@ def cpu_baseline(p, nslices_sample):
 
 
 def run_extras(dev):
-    """Untimed runs of the other workloads (3D, batched, adjoint).  Their
+    """Untimed runs: the 2D fine sweep at every sliding-window depth, and the
+    other workloads (3D, batched, adjoint).  The workloads'
     agreement with the oracle at these sizes is checked by the GPU tests
     (test_gpu_fullsize, test_gpu_batched, test_gpu_adjoint); here each result
     is compared with the library's own serial fine integration."""
@@ -180,6 +183,39 @@ def run_extras(dev):
     import workloads
 
     out = {}
+    # ---- fine sweep of the 2D workload (64 states x 83 steps) by every
+    # sliding-window depth D: bytes per lattice update fall as 16/D while the
+    # arithmetic per pass grows with D
+    p = workloads.heat2d()
+    N = p.nslices
+    prob = pr.Problem(pr.config_of(p))
+    info = prob.info()
+    xs = torch.rand((N, p.n, p.n), dtype=torch.float64, device=dev)
+    ys = torch.empty_like(xs)
+    npts = N * p.n * p.n
+    table = []
+    for d, rows, xp, sw in pr.fine_shapes(2):
+        if not sw or xp != 2:
+            continue
+        prob.set_fine_shape(d, rows, xp)
+        prob.apply_fine(xs, ys, N, info.m)
+        torch.cuda.synchronize()
+        reps = 5
+        t = time.perf_counter()
+        for _ in range(reps):
+            prob.apply_fine(xs, ys, N, info.m)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / reps * 1e3
+        passes = -(-info.m // d)
+        gbs = passes * 16.0 * npts / (ms * 1e-3) / 1e9
+        table.append({"kernel": f"k_fine2d_sw<{xp},{d}>", "D": d, "rows": "auto" if rows >= 1000 else rows,
+                      "passes": passes, "sweep_ms": ms, "glups": npts * info.m / (ms * 1e-3) / 1e9,
+                      "alg_bytes_per_lup": passes * 16.0 / info.m, "alg_GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS})
+    out["fine_depth"] = {"workload": "heat2d n=1024^2, 64 states x 83 explicit steps", "shapes": table}
+    prob.close()
+    del xs, ys
+    torch.cuda.empty_cache()
+
     # ---- 3D: 256^3, 128 slices (m = 1 explicit step per slice)
     p = workloads.heat3d()
     N = p.nslices
@@ -414,15 +450,15 @@ def main():
 
     # ---- roofline objects (algorithmic bytes per launch / live event durations)
     # Algorithmic bytes per point: F pass 16 (read + write the state).  2D
-    # preconditioned CG (sync sweep and async teams): iteration 96 (reads r,
-    # w, s, x, u, p; writes the same six), set-up 48 (read b, write x, r0;
-    # read r0, write u0, w0).  Unpreconditioned 2D CG (cg_precond = -1;
+    # preconditioned CG (sync sweep and async teams): iteration 64 (reads r,
+    # u, p, x; writes the same four), set-up 40 (read b, write x, r0; read r0,
+    # write u0).  Unpreconditioned 2D CG (cg_precond = -1;
     # products recomputed from r and p): iteration 48 (reads r, p_old, x;
     # writes p, x, r'), set-up 24.  Correction 48 (read v, w_new, w_old,
     # lambda_old, write lambda, w).
     D = info.tb_depth
     passes = -(-m // D)
-    cg_it_b, cg_set_b = (96.0, 48.0) if info.cg_precond else (48.0, 24.0)
+    cg_it_b, cg_set_b = (64.0, 40.0) if info.cg_precond else (48.0, 24.0)
     fine_kernel = fine_kernel_name(info)
     rl = {}
     if rec["sync"]:

@@ -230,7 +230,7 @@ int  pr_apply_coarse(pr_problem *h, const double *in, double *out, int count, lo
  * problem *cfg (2D or 3D, CG; the same solver and launch as pr_apply_coarse,
  * hence the same bits), with no handle: every scratch buffer (CG vectors,
  * reduction slots, team counters) lives in a fixed device array of the
- * library, 64 MiB per device, held from the first call on a device until the
+ * library, 48 MiB per device, held from the first call on a device until the
  * process ends.  A state may hold at most 2^20 points (n <= 1024 in 2D,
  * n <= 101 in 3D); larger states, 1D problems, aliasing or NULL buffers are
  * PR_EINVAL.  device: HIP ordinal; stream: hipStream_t or NULL; in, out:

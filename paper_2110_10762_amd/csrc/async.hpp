@@ -85,7 +85,7 @@ struct AsyncWork {
     long long *tbc = nullptr;
     double *tred = nullptr;
     double *cgr = nullptr, *cgr1 = nullptr, *cgp0 = nullptr, *cgp1 = nullptr, *cgb = nullptr;
-    double *cgw0 = nullptr, *cgw1 = nullptr, *cgs0 = nullptr, *cgs1 = nullptr;   // 2D preconditioned CG
+    double *cgw0 = nullptr, *cgw1 = nullptr;   // 2D preconditioned CG: u (r and p shared)
     int *drop = nullptr, *reset = nullptr;   // failure injection, [N+1] each
     double *lam0 = nullptr;                  // [(N+1) npts] initial iterate (resets only)
     unsigned long long *counters = nullptr;
@@ -131,7 +131,7 @@ struct AsyncArgs {
     long long *tbc;          // [nteams * 16] leader broadcasts
     double *tred;            // [nteams * 8 * maxtsz]
     double *cgr, *cgr1, *cgp0, *cgp1;   // [nteams * cgs]
-    double *cgw0, *cgw1, *cgs0, *cgs1;  // [nteams * cgs], 2D preconditioned CG only
+    double *cgw0, *cgw1;                // [nteams * cgs], 2D preconditioned CG only
     long long cgs;               // per-team stride of the CG vectors
     Control *ctl;
     unsigned long long *counters;   // cg iterations, coarse solves, skipped solves, copy retries, idle rounds
@@ -361,8 +361,7 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
         if constexpr (DIM == 2 && PCG) {
             // the preconditioned CG (marching sweeps of a whole iteration)
             const long long o = (long long)a.team_of[blockIdx.x] * a.cgs;
-            const CGWorkP wkp{{wk2.r[0], wk2.r[1]}, {a.cgw0 + o, a.cgw1 + o}, {a.cgs0 + o, a.cgs1 + o},
-                              wk2.p[0], wk2.p[1], wk2.red};
+            const CGWorkP wkp{{wk2.r[0], wk2.r[1]}, {a.cgw0 + o, a.cgw1 + o}, {wk2.p[0], wk2.p[1]}, wk2.red};
             it = cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_TEAM, 1>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wkp,
                                                            abs_thresh2);
         } else if constexpr (DIM == 2)

@@ -55,7 +55,7 @@ struct BatchArgs {
     long long *tbc;
     double *tred;
     double *wn, *cgr, *cgr1, *cgp0, *cgp1, *d0, *d1;   // [nteams][maxnpts]
-    double *cgw0, *cgw1, *cgs0, *cgs1;                 // [nteams][maxnpts], preconditioned CG only
+    double *cgw0, *cgw1;                               // [nteams][maxnpts], preconditioned CG only
     long long maxnpts;
     const int *order;
     unsigned *queue;
@@ -163,12 +163,10 @@ __global__ __launch_bounds__(BLOCK, PCG ? 2 : 3) void k_bsweep(BatchArgs a) {
             CGWorkPT wkp;
             wkp.r[0] = a.cgr + o;
             wkp.r[1] = a.cgr1 + o;
-            wkp.w[0] = a.cgw0 + o;
-            wkp.w[1] = a.cgw1 + o;
-            wkp.s[0] = a.cgs0 + o;
-            wkp.s[1] = a.cgs1 + o;
-            wkp.u = a.cgp0 + o;
-            wkp.p = a.cgp1 + o;
+            wkp.u[0] = a.cgw0 + o;
+            wkp.u[1] = a.cgw1 + o;
+            wkp.p[0] = a.cgp0 + o;
+            wkp.p[1] = a.cgp1 + o;
             wkp.red = red;
             ok = team_coarse_sweep<2>(tm, P.g, P.s, P.cg_tol, P.cg_maxit, P.npts, init ? 1 : k, P.N, init ? -1 : k,
                                       init, P.incr != 0, SB, wkp, dmax, its, lds);
@@ -217,7 +215,7 @@ struct BatchWork {
     unsigned *tctr = nullptr, *queue = nullptr;
     long long *tbc = nullptr;
     double *tred = nullptr, *wn = nullptr, *cgr = nullptr, *cgr1 = nullptr, *cgp0 = nullptr, *cgp1 = nullptr;
-    double *cgw0 = nullptr, *cgw1 = nullptr, *cgs0 = nullptr, *cgs1 = nullptr;
+    double *cgw0 = nullptr, *cgw1 = nullptr;
     bool pcg = false;   // coarse solves by the preconditioned CG
     double *d0 = nullptr, *d1 = nullptr;
     long long maxnpts = 0, total = 0;

@@ -203,6 +203,19 @@ __device__ __forceinline__ double be_point(double yc, double nsum, double twod, 
     return __builtin_fma(-s, lap, yc);
 }
 
+// Row-segment length of a marching sweep: `strips` columns of waves (times
+// planes in 3D) over n rows, shared by `waves` waves, one (strip, segment)
+// unit per wave and round.  The shortest segment of at least minseg rows
+// whose units all fit in one round; a whole strip when even one segment per
+// strip leaves more units than waves.  (Rounding the rows per wave up before
+// the segments per strip can leave a few units for a second round, which
+// doubles the sweep's critical path.)
+__device__ __forceinline__ int march_seg(int n, long long strips, int waves, int minseg) {
+    const long long fit = waves / strips;   // segments per strip in one round
+    const int seg = fit > 0 ? (int)((n + fit - 1) / fit) : n;
+    return max(min(minseg, n), seg);
+}
+
 // ------------------------------------------------------------------ CG
 struct CGWork {
     double *r, *p0, *p1;   // [npts] each
@@ -333,10 +346,8 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
     const int waves = size * nwaves();
     const int wid = rank * nwaves() + wave_id();
     const bool use_b = MODE == CG3_A && !first;
-    // y-segments: about one (strip, plane, segment) unit per wave, at least 16 rows
-    const long long rows = (long long)n * n * g.cpr;
-    const int per = (int)min((long long)n, (rows + waves - 1) / waves);
-    const int seg = max(min(16, n), per);
+    // y-segments: one (strip, plane, segment) unit per wave, at least 16 rows
+    const int seg = march_seg(n, (long long)g.cpr * n, waves, 16);
     const int nseg = (n + seg - 1) / seg;
     const long long units = (long long)g.cpr * n * nseg;
     for (long long u = wid; u < units; u += waves) {
@@ -849,9 +860,8 @@ __device__ __forceinline__ void cg2_sweep_sw(const Geom &g, int rank, int size, 
     const bool l0 = lane == 0, l63 = lane == WAVE - 1;
     const int waves = size * nwaves();
     const int wid = rank * nwaves() + wave_id();
-    // segments of rows: about one (strip, segment) unit per wave, at least MINSEG rows
-    const int per = (int)(((long long)n * g.cpr + waves - 1) / waves);
-    const int seg = max(MINSEG, per);
+    // segments of rows: one (strip, segment) unit per wave, at least MINSEG rows
+    const int seg = march_seg(n, g.cpr, waves, MINSEG);
     const int nseg = (n + seg - 1) / seg;
     const int units = g.cpr * nseg;
     for (int u = wid; u < units; u += waves) {

@@ -120,7 +120,7 @@ struct pr_problem {
     double *v = nullptr, *w = nullptr, *tmp = nullptr, *wn = nullptr, *d0 = nullptr, *d1 = nullptr;
     double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *red = nullptr;
     double *cg_r1 = nullptr;   // second residual buffer of the 2D one-synchronisation CG
-    double *cg_w0 = nullptr, *cg_w1 = nullptr, *cg_s0 = nullptr, *cg_s1 = nullptr;   // 2D preconditioned CG
+    double *cg_w0 = nullptr, *cg_w1 = nullptr;   // 2D preconditioned CG: u (p and r shared)
     double *inv_tab = nullptr;        // 1D Thomas factors, padded
     double *inv_tab_f = nullptr;      // 1D Thomas factors of an implicit fine step (s = theta r)
     // implicit fine steps on many states (2D/3D): per-team tmp, rhs, CG set
@@ -532,7 +532,7 @@ static SweepArgs sweep_args(pr_problem *h, const Prob &P, double *lam) {
     a.cg_maxit = P.cg_maxit;
     a.wk = CGWork{h->cg_r, h->cg_p0, h->cg_p1, h->red};
     a.wk2 = CGWork2{{h->cg_r, h->cg_r1}, {h->cg_p0, h->cg_p1}, h->red};
-    a.wkp = CGWorkP{{h->cg_r, h->cg_r1}, {h->cg_w0, h->cg_w1}, {h->cg_s0, h->cg_s1}, h->cg_p0, h->cg_p1, h->red};
+    a.wkp = CGWorkP{{h->cg_r, h->cg_r1}, {h->cg_w0, h->cg_w1}, {h->cg_p0, h->cg_p1}, h->red};
     a.ctr = h->ctr;
     a.ctl = h->ctl;
     return a;
@@ -591,8 +591,6 @@ static int alloc_sync(pr_problem *h) {
         if ((rc = alloc_t(h, &h->cg_r1, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_w0, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->cg_w1, P.npts))) return rc;
-        if ((rc = alloc_t(h, &h->cg_s0, P.npts))) return rc;
-        if ((rc = alloc_t(h, &h->cg_s1, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->d0, P.npts))) return rc;
         if ((rc = alloc_t(h, &h->d1, P.npts))) return rc;
     }
@@ -849,7 +847,7 @@ extern "C" int pr_apply_coarse(pr_problem *h, const double *in, double *out, int
     int maxit = P.cg_maxit;
     CGWork wk{h->cg_r, h->cg_p0, h->cg_p1, h->red};
     CGWork2 wk2{{h->cg_r, h->cg_r1}, {h->cg_p0, h->cg_p1}, h->red};
-    CGWorkP wkp{{h->cg_r, h->cg_r1}, {h->cg_w0, h->cg_w1}, {h->cg_s0, h->cg_s1}, h->cg_p0, h->cg_p1, h->red};
+    CGWorkP wkp{{h->cg_r, h->cg_r1}, {h->cg_w0, h->cg_w1}, {h->cg_p0, h->cg_p1}, h->red};
     unsigned *ctr = h->ctr;
     Control *ctl = h->ctl;
     unsigned long long *ci = h->iscal;
@@ -874,7 +872,7 @@ constexpr long long kStaticPts = 1ll << 20;          // largest state: 2^20 poin
 constexpr long long kStaticRed = 2 * 4096;           // reduction slots (doubles)
 constexpr long long kStaticCtr = 4096 / 2;           // team counters: 4096 words
 constexpr long long kStaticCtl = 8;                  // Control + iteration counter
-constexpr long long kStaticDoubles = 8 * kStaticPts + kStaticRed + kStaticCtr + kStaticCtl;
+constexpr long long kStaticDoubles = 6 * kStaticPts + kStaticRed + kStaticCtr + kStaticCtl;
 static __device__ __align__(256) double scratch[kStaticDoubles];
 
 static std::mutex g_static_mu;
@@ -933,9 +931,8 @@ extern "C" int pr_apply_coarse_static(const pr_config *cfg, int device, void *st
     if (count == 0) return PR_OK;
     hipStream_t st = (hipStream_t)stream;
     double *r0 = base, *r1 = base + kStaticPts, *p0 = base + 2 * kStaticPts, *p1 = base + 3 * kStaticPts;
-    double *w0 = base + 4 * kStaticPts, *w1 = base + 5 * kStaticPts, *s0 = base + 6 * kStaticPts,
-           *s1 = base + 7 * kStaticPts;
-    double *red = base + 8 * kStaticPts;
+    double *w0 = base + 4 * kStaticPts, *w1 = base + 5 * kStaticPts;
+    double *red = base + 6 * kStaticPts;
     unsigned *ctr = (unsigned *)(red + kStaticRed);
     Control *ctl = (Control *)(red + kStaticRed + kStaticCtr);
     unsigned long long *ci = (unsigned long long *)(red + kStaticRed + kStaticCtr + 2);
@@ -952,7 +949,7 @@ extern "C" int pr_apply_coarse_static(const pr_config *cfg, int device, void *st
     int maxit = P.cg_maxit;
     CGWork wk{r0, p0, p1, red};
     CGWork2 wk2{{r0, r1}, {p0, p1}, red};
-    CGWorkP wkp{{r0, r1}, {w0, w1}, {s0, s1}, p0, p1, red};
+    CGWorkP wkp{{r0, r1}, {w0, w1}, {p0, p1}, red};
     void *args[] = {&in, &out, &npts, &count, &g, &s, &tol, &maxit, &wk, &wk2, &wkp, &ctr, &ctl, &ci};
     const void *fn = P.dim == 3 ? (const void *)k_coarse_cg_batch<3>
                                 : (P.pcg ? (const void *)k_coarse_cg_batch<2, true> : (const void *)k_coarse_cg_batch<2>);

@@ -14,30 +14,32 @@
 // PD stencil passes with no inner product: it needs no synchronisation.
 //
 // Iteration (Chronopoulos-Gear form of preconditioned CG: one team barrier
-// per iteration, the three inner products reduced together), with
-// u = M^-1 r, w = A u, s = A p kept as vectors:
-//     p_i = u_i + beta_i p_{i-1},   s_i = w_i + beta_i s_{i-1}
+// per iteration, the three inner products reduced together):
+//     p_i = u_i + beta_i p_{i-1},   s_i = A p_i
 //     x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i
 //     u_{i+1} = p(A) r_{i+1},       w_{i+1} = A u_{i+1}
 //     gamma = (r_{i+1}, u_{i+1}), delta = (w_{i+1}, u_{i+1}), rho = (r_{i+1}, r_{i+1})
 //     beta_{i+1} = gamma_{i+1} / gamma_i
 //     alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1} / alpha_i)
-// Start and stop as the unpreconditioned solvers: x0 = b and
+// Only r, u, p and x are stored; s = A p and w = A u are formed where they
+// are used.  Start and stop as the unpreconditioned solvers: x0 = b and
 // ||r||_2 <= tol ||b||_2 (or x0 = 0 and ||r||_2^2 <= abs_thresh2 for the
 // increment form), rho being the true recurrence residual of CG.
 //
 // One sweep does a whole iteration.  A wave takes a strip of 64 columns and
-// a segment of rows and marches down it: each input row brings r_i, w_i and
-// s_{i-1}, from which s_i and r_{i+1} are formed at once; the PD Chebyshev
-// levels and the level forming w = A u each lag one row behind the one
-// before (two rows of the stencil operand and one row of the pointwise terms
-// held per level), so the output row is H = PD + 1 rows behind the input.
-// The strip's outer H columns and the segment's H halo rows on either side
-// are recomputed, not exchanged.  Out-of-domain rows and columns are read
-// from the odd extension of each vector, which every step commutes with, so
-// the zero Dirichlet values need no masks (as in the fine kernels).
-// HBM traffic per point and iteration: r, w, s, x, u, p read, the same six
-// written (96 B); the halo re-reads hit the caches.
+// a segment of rows and marches down it: each input row brings r_i, u_i and
+// p_{i-1}, from which p_i is formed at once; a level forming s_i = A p_i and
+// r_{i+1}, the PD Chebyshev levels and the level forming w = A u each lag one
+// row behind the one before (two rows of the stencil operand and one row of
+// the pointwise terms held per level), so the output row, where x, p_i and
+// u_{i+1} are formed and stored, is H = PD + 2 rows behind the input.  The
+// strip's outer H columns and the segment's H halo rows on either side are
+// recomputed, not exchanged.  Out-of-domain rows and columns are read from
+// the odd extension of each vector, which every step commutes with, so the
+// zero Dirichlet values need no masks (as in the fine kernels).
+// HBM traffic per point and iteration: r, u, p, x read, the same four
+// written (64 B); the halo re-reads and the output row's second reads of u
+// and p hit the caches.
 #pragma once
 #include "fine.hpp"
 #include "coarse.hpp"
@@ -45,7 +47,7 @@
 namespace pr {
 
 // Chebyshev polynomial degree of the preconditioner, and the shortest row
-// segment a wave of the marching sweep takes (the H = degree + 1 halo rows on
+// segment a wave of the marching sweep takes (the H = degree + 2 halo rows on
 // either side of a segment are recomputed).
 // Measured on the 1024^2 workload (sync / async solve): degree 4 with
 // segments of 16 / 24 rows 495 / 488 ms, degree 6 with 8 / 16 rows 396 / 400
@@ -55,8 +57,7 @@ constexpr int PCG_MINSEG_GPU = 8;     // a team spanning the GPU (many waves per
 constexpr int PCG_MINSEG_TEAM = 16;   // teams of a few XCDs or less
 
 struct CGWorkP {
-    double *r[2], *w[2], *s[2];   // [npts] each, read with halos: double-buffered
-    double *u, *p;                // [npts] each, read and written only at the point: in place
+    double *r[2], *u[2], *p[2];   // [npts] each, read with halos: double-buffered
     double *red;                  // [8 * team size] reduction slots
 };
 // The same vectors, for a team of a few workgroups (longer row segments).
@@ -107,34 +108,35 @@ __device__ __forceinline__ void cgp_start(const Geom &g, const ChunkRange &cr, d
     }
 }
 
-// Raw loads of one march step: input row (r, w, s) and output row (x, u, p).
+// Raw loads of one march step: input row (r, u, p_old) and output row (x,
+// u, p_old).
 struct PRow {
-    double r, w, s, x, u, p;
+    double r, u, p, x, uo, po;
 };
 
-// One iteration (or, SETUP, the first preconditioning u0 = p(A) r0, w0 = A u0)
-// of the team's share of the state; accumulates the partial sums of
-// (r', u'), (w', u') and (r', r') over the points the wave owns.
+// One iteration (or, SETUP, the first preconditioning u0 = p(A) r0 with
+// w0 = A u0, p taken as 0) of the team's share of the state; accumulates the
+// partial sums of (r', u'), (w', u') and (r', r') over the points the wave
+// owns.
 template <int PD, int PF, bool SETUP>
 __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int minseg, double s,
                                           const Cheb<PD> &cc, double alpha, double beta, bool first,
-                                          const double *__restrict__ rin, const double *__restrict__ win,
-                                          const double *__restrict__ sinp, double *__restrict__ rout,
-                                          double *__restrict__ wout, double *__restrict__ sout,
-                                          double *__restrict__ x, double *__restrict__ u,
-                                          double *__restrict__ p, double &ga, double &de, double &rr) {
-    constexpr int H = PD + 1;            // stencil levels between input and output row
+                                          const double *__restrict__ rin, const double *__restrict__ uin,
+                                          const double *__restrict__ pin, double *__restrict__ rout,
+                                          double *__restrict__ uout, double *__restrict__ pout,
+                                          double *__restrict__ x, double &ga, double &de, double &rr) {
+    constexpr int H = PD + 2;            // stencil levels between input and output row
     constexpr int W = WAVE - 2 * H;      // columns a strip owns
     const int n = g.n;
     const int lane = threadIdx.x & (WAVE - 1);
     const int waves = size * nwaves();
     const int wid = rank * nwaves() + wave_id();
     const int nsx = (n + W - 1) / W;
-    // segments of rows: about one (strip, segment) unit per wave, at least minseg rows
-    const int per = (int)(((long long)n * nsx + waves - 1) / waves);
-    const int seg = max(minseg, per);
+    // segments of rows: one (strip, segment) unit per wave, at least minseg rows
+    const int seg = march_seg(n, nsx, waves, minseg);
     const int nseg = (n + seg - 1) / seg;
     const int units = nsx * nseg;
+    const bool read_p = !SETUP && !first;   // p_{-1} = 0
     for (int un = wid; un < units; un += waves) {
         const int sx = un % nsx;   // strips of the same rows side by side
         const int ya = (un / nsx) * seg;
@@ -143,13 +145,14 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
         double xsg;
         const int xi = reflect(xcol, n, xsg);
         const bool own = lane >= H && lane < H + W && xcol < n;
+        double pa = 0.0, pb = 0.0, rd = 0.0;   // p_i at rows k-2, k-1; r_i at row k-1
         double w0[PD], w1[PD], Rd[PD], Xd[PD];
 #pragma unroll
         for (int j = 0; j < PD; ++j) w0[j] = w1[j] = Rd[j] = Xd[j] = 0.0;
         double ua = 0.0, ub = 0.0;
-        double DR[H], DS[H];   // r_{i+1} and s_i of the last H input rows, oldest first
+        double DR[H - 1];   // r_{i+1} of the last H - 1 rows it was formed for, oldest first
 #pragma unroll
-        for (int j = 0; j < H; ++j) DR[j] = DS[j] = 0.0;
+        for (int j = 0; j < H - 1; ++j) DR[j] = 0.0;
         const int nrows = yb - ya + 2 * H;
         const int k0 = ya - H;
         PRow ring[PF];
@@ -164,13 +167,13 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
             const long long rb = (long long)yi * n;
             w.r = (rin + rb)[xi];
             if constexpr (!SETUP) {
-                w.w = (win + rb)[xi];
-                w.s = first ? 0.0 : (sinp + rb)[xi];
+                w.u = (uin + rb)[xi];
+                w.p = read_p ? (pin + rb)[xi] : 0.0;
                 const int y = min(max(kk - H, ya), yb - 1);
                 const long long ob = (long long)y * n;
                 w.x = (x + ob)[xi];
-                w.u = (u + ob)[xi];
-                w.p = first ? 0.0 : (p + ob)[xi];
+                w.uo = (uin + ob)[xi];
+                w.po = read_p ? (pin + ob)[xi] : 0.0;
             }
             sg = ys * xsg;
         };
@@ -187,23 +190,21 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
                 if (t >= nrows) break;
                 const int k = k0 + t;
                 const double sg = rsg[q];
-                // input row k: s_i and r_{i+1} (set-up: r0)
-                double rn, sn = 0.0;
-                if constexpr (SETUP) {
-                    rn = sg * ring[q].r;
-                } else {
-                    sn = __builtin_fma(beta, sg * ring[q].s, sg * ring[q].w);
-                    rn = __builtin_fma(-alpha, sn, sg * ring[q].r);
-                }
-                const double rf = DR[0], sf = DS[0];   // row k - H
+                // input row k: p_i (set-up: 0) and r_i
+                const double pn = SETUP ? 0.0 : __builtin_fma(beta, sg * ring[q].p, sg * ring[q].u);
+                const double rk = sg * ring[q].r;
+                // s_i = A p_i and r_{i+1} at row k - 1 (set-up: s = 0, alpha = 0: r0)
+                const double pl = from_lower_lane(pb), pr = from_upper_lane(pb);
+                const double sv = be_point(pb, (pa + pn) + (pl + pr), 4.0, s);
+                const double rn = __builtin_fma(-alpha, sv, rd);
+                pa = pb;
+                pb = pn;
+                rd = rk;
+                const double rf = DR[0];   // r_{i+1} at row k - H
 #pragma unroll
-                for (int j = 0; j + 1 < H; ++j) {
-                    DR[j] = DR[j + 1];
-                    DS[j] = DS[j + 1];
-                }
-                DR[H - 1] = rn;
-                DS[H - 1] = sn;
-                // Chebyshev levels: level j+1 forms row k-1-j from rows k-2-j..k-j of level j
+                for (int j = 0; j + 1 < H - 1; ++j) DR[j] = DR[j + 1];
+                DR[H - 2] = rn;
+                // Chebyshev levels: level j+1 forms row k-2-j from rows k-3-j..k-1-j of level j
                 double dn = rn * cc.inv_theta, Rn = rn, Xn = dn;
 #pragma unroll
                 for (int j = 0; j < PD; ++j) {
@@ -220,7 +221,7 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
                     Rn = Rj;
                     Xn = Xj;
                 }
-                // u = p(A) r' reached row k - PD; w = A u at row k - H
+                // u = p(A) r' reached row k - 1 - PD; w = A u at row k - H
                 const double l = from_lower_lane(ub), r = from_upper_lane(ub);
                 const double wn = be_point(ub, (ua + Xn) + (l + r), 4.0, s);
                 const double un = ub;
@@ -230,14 +231,12 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
                 if (y >= ya && y < yb && own) {
                     const long long i = (long long)y * n + xcol;
                     if constexpr (!SETUP) {
-                        const double pi = __builtin_fma(beta, ring[q].p, ring[q].u);
+                        const double pi = __builtin_fma(beta, ring[q].po, ring[q].uo);
                         x[i] = __builtin_fma(alpha, pi, ring[q].x);
-                        p[i] = pi;
-                        sout[i] = sf;
+                        pout[i] = pi;
                         rout[i] = rf;
                     }
-                    u[i] = un;
-                    wout[i] = wn;
+                    uout[i] = un;
                     ga = __builtin_fma(rf, un, ga);
                     de = __builtin_fma(wn, un, de);
                     rr = __builtin_fma(rf, rf, rr);
@@ -265,7 +264,7 @@ __device__ int cg_team_2d_p(Team &tm, const Geom &g, double s, double tol, int m
     if (!team_sync(tm)) return -1;
     double part[4] = {0.0, 0.0, 0.0, bb}, tot[4];
     cgp_sweep<PD, PF, true>(g, tm.rank, tm.size, MINSEG, s, cc, 0.0, 0.0, true, wk.r[0], nullptr, nullptr,
-                            nullptr, wk.w[0], nullptr, x, wk.u, wk.p, part[0], part[1], part[2]);
+                            nullptr, wk.u[0], nullptr, x, part[0], part[1], part[2]);
     if (!team_reduce_n<4>(tm, part, wk.red, tot)) return -1;
     double gamma = tot[0], rho = tot[2];
     const double thresh = from_zero ? (abs_thresh2 > 0.0 ? abs_thresh2 : tol * tol * tot[3]) : tol * tol * tot[3];
@@ -274,9 +273,8 @@ __device__ int cg_team_2d_p(Team &tm, const Geom &g, double s, double tol, int m
     int it = 0;
     while (it < maxit && rho > thresh) {
         double pp[3] = {0.0, 0.0, 0.0}, tt[3];
-        cgp_sweep<PD, PF, false>(g, tm.rank, tm.size, MINSEG, s, cc, alpha, beta, it == 0, wk.r[cur], wk.w[cur],
-                                 wk.s[cur], wk.r[cur ^ 1], wk.w[cur ^ 1], wk.s[cur ^ 1], x, wk.u, wk.p, pp[0],
-                                 pp[1], pp[2]);
+        cgp_sweep<PD, PF, false>(g, tm.rank, tm.size, MINSEG, s, cc, alpha, beta, it == 0, wk.r[cur], wk.u[cur],
+                                 wk.p[cur], wk.r[cur ^ 1], wk.u[cur ^ 1], wk.p[cur ^ 1], x, pp[0], pp[1], pp[2]);
         if (!team_reduce_n<3>(tm, pp, wk.red, tt)) return -1;
         ++it;
         beta = tt[0] / gamma;
