@@ -118,13 +118,18 @@ struct PRow {
 // w0 = A u0, p taken as 0) of the team's share of the state; accumulates the
 // partial sums of (r', u'), (w', u') and (r', r') over the points the wave
 // owns.
-template <int PD, int PF, bool SETUP>
+template <int PD, int PF, bool SETUP, bool SKIP>
 __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int minseg, double s,
                                           const Cheb<PD> &cc, double alpha, double beta, bool first,
                                           const double *__restrict__ rin, const double *__restrict__ uin,
                                           const double *__restrict__ pin, double *__restrict__ rout,
                                           double *__restrict__ uout, double *__restrict__ pout,
                                           double *__restrict__ x, double &ga, double &de, double &rr) {
+    // Rounding exactly as written (no contraction of the remaining products
+    // and sums into fused operations): a point's values come out the same
+    // bits in every segment and strip that recomputes them, whatever code
+    // the compiler makes of the step.
+#pragma clang fp contract(off)
     constexpr int H = PD + 2;            // stencil levels between input and output row
     constexpr int W = WAVE - 2 * H;      // columns a strip owns
     const int n = g.n;
@@ -183,52 +188,63 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
             rsg[q] = 0.0;
             if (q < nrows) issue(k0 + q, ring[q], rsg[q]);
         }
-        for (int tb = 0; tb < nrows; tb += PF) {
-#pragma unroll
-            for (int q = 0; q < PF; ++q) {
-                const int t = tb + q;
-                if (t >= nrows) break;
-                const int k = k0 + t;
-                const double sg = rsg[q];
-                // input row k: p_i (set-up: 0) and r_i
-                const double pn = SETUP ? 0.0 : __builtin_fma(beta, sg * ring[q].p, sg * ring[q].u);
-                const double rk = sg * ring[q].r;
-                // s_i = A p_i and r_{i+1} at row k - 1 (set-up: s = 0, alpha = 0: r0)
+        // One march step t (input row k = k0 + t, ring slot q).  Level l of the
+        // march (1: s = A p, 2 .. H - 1: Chebyshev, H: w = A u) works on row
+        // k0 + t - l, and the output rows depend on it only from t >= 2 l
+        // on.  SKIP: until then a level skips its arithmetic (a third of the
+        // levels' work in a 12-row segment) while its input rows still move
+        // through the registers; needed values are unchanged.  (The tests are
+        // wave-uniform; a second copy of the step without them for t >= 2 H
+        // spills registers, and so do the tests themselves in the kernels
+        // whose other phases hold many registers.)
+        auto step = [&](const int t, const int q) {
+            const int k = k0 + t;
+            const double sg = rsg[q];
+            // input row k: p_i (set-up: 0) and r_i
+            const double pn = SETUP ? 0.0 : __builtin_fma(beta, sg * ring[q].p, sg * ring[q].u);
+            const double rk = sg * ring[q].r;
+            // s_i = A p_i and r_{i+1} at row k - 1 (set-up: s = 0, alpha = 0: r0)
+            double rn = 0.0;
+            if (!SKIP || t >= 2) {
                 const double pl = from_lower_lane(pb), pr = from_upper_lane(pb);
                 const double sv = be_point(pb, (pa + pn) + (pl + pr), 4.0, s);
-                const double rn = __builtin_fma(-alpha, sv, rd);
-                pa = pb;
-                pb = pn;
-                rd = rk;
-                const double rf = DR[0];   // r_{i+1} at row k - H
+                rn = __builtin_fma(-alpha, sv, rd);
+            }
+            pa = pb;
+            pb = pn;
+            rd = rk;
+            const double rf = DR[0];   // r_{i+1} at row k - H
 #pragma unroll
-                for (int j = 0; j + 1 < H - 1; ++j) DR[j] = DR[j + 1];
-                DR[H - 2] = rn;
-                // Chebyshev levels: level j+1 forms row k-2-j from rows k-3-j..k-1-j of level j
-                double dn = rn * cc.inv_theta, Rn = rn, Xn = dn;
+            for (int j = 0; j + 1 < H - 1; ++j) DR[j] = DR[j + 1];
+            DR[H - 2] = rn;
+            // Chebyshev levels: level j+1 forms row k-2-j from rows k-3-j..k-1-j of level j
+            double dn = rn * cc.inv_theta, Rn = rn, Xn = dn;
 #pragma unroll
-                for (int j = 0; j < PD; ++j) {
+            for (int j = 0; j < PD; ++j) {
+                double dj = 0.0, Rj = 0.0, Xj = 0.0;
+                if (!SKIP || t >= 2 * (j + 2)) {
                     const double l = from_lower_lane(w1[j]), r = from_upper_lane(w1[j]);
                     const double ad = be_point(w1[j], (w0[j] + dn) + (l + r), 4.0, s);
-                    const double Rj = Rd[j] - ad;
-                    const double dj = __builtin_fma(cc.c2[j], Rj, cc.c1[j] * w1[j]);
-                    const double Xj = Xd[j] + dj;
-                    w0[j] = w1[j];
-                    w1[j] = dn;
-                    Rd[j] = Rn;
-                    Xd[j] = Xn;
-                    dn = dj;
-                    Rn = Rj;
-                    Xn = Xj;
+                    Rj = Rd[j] - ad;
+                    dj = __builtin_fma(cc.c2[j], Rj, cc.c1[j] * w1[j]);
+                    Xj = Xd[j] + dj;
                 }
-                // u = p(A) r' reached row k - 1 - PD; w = A u at row k - H
+                w0[j] = w1[j];
+                w1[j] = dn;
+                Rd[j] = Rn;
+                Xd[j] = Xn;
+                dn = dj;
+                Rn = Rj;
+                Xn = Xj;
+            }
+            // u = p(A) r' reached row k - 1 - PD; w = A u and the output at row
+            // k - H (inside the segment from t = 2 H on)
+            if (t >= 2 * H) {
                 const double l = from_lower_lane(ub), r = from_upper_lane(ub);
                 const double wn = be_point(ub, (ua + Xn) + (l + r), 4.0, s);
                 const double un = ub;
-                ua = ub;
-                ub = Xn;
                 const int y = k - H;
-                if (y >= ya && y < yb && own) {
+                if (y < yb && own) {
                     const long long i = (long long)y * n + xcol;
                     if constexpr (!SETUP) {
                         const double pi = __builtin_fma(beta, ring[q].po, ring[q].uo);
@@ -241,7 +257,16 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
                     de = __builtin_fma(wn, un, de);
                     rr = __builtin_fma(rf, rf, rr);
                 }
-                if (t + PF < nrows) issue(k + PF, ring[q], rsg[q]);
+            }
+            ua = ub;
+            ub = Xn;
+            if (t + PF < nrows) issue(k + PF, ring[q], rsg[q]);
+        };
+        for (int tb = 0; tb < nrows; tb += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                if (tb + q >= nrows) break;
+                step(tb + q, q);
             }
         }
     }
@@ -251,7 +276,7 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
 // start and stop rules as cg_team_dim (abs_thresh2 < 0: x0 = b, relative
 // stop; >= 0: x0 = 0, absolute stop).  Returns the iteration count, or -1 if
 // the launch was aborted.  x must not alias b or the work vectors.
-template <int PD, int MINSEG, int PF = 4>
+template <int PD, int MINSEG, int PF = 4, bool SKIP = false>
 __device__ int cg_team_2d_p(Team &tm, const Geom &g, double s, double tol, int maxit,
                             const double *__restrict__ b, double *__restrict__ x, const CGWorkP &wk,
                             double abs_thresh2) {
@@ -263,7 +288,7 @@ __device__ int cg_team_2d_p(Team &tm, const Geom &g, double s, double tol, int m
     cgp_start(g, cr, s, from_zero, b, x, wk.r[0], bb);
     if (!team_sync(tm)) return -1;
     double part[4] = {0.0, 0.0, 0.0, bb}, tot[4];
-    cgp_sweep<PD, PF, true>(g, tm.rank, tm.size, MINSEG, s, cc, 0.0, 0.0, true, wk.r[0], nullptr, nullptr,
+    cgp_sweep<PD, PF, true, SKIP>(g, tm.rank, tm.size, MINSEG, s, cc, 0.0, 0.0, true, wk.r[0], nullptr, nullptr,
                             nullptr, wk.u[0], nullptr, x, part[0], part[1], part[2]);
     if (!team_reduce_n<4>(tm, part, wk.red, tot)) return -1;
     double gamma = tot[0], rho = tot[2];
@@ -273,7 +298,7 @@ __device__ int cg_team_2d_p(Team &tm, const Geom &g, double s, double tol, int m
     int it = 0;
     while (it < maxit && rho > thresh) {
         double pp[3] = {0.0, 0.0, 0.0}, tt[3];
-        cgp_sweep<PD, PF, false>(g, tm.rank, tm.size, MINSEG, s, cc, alpha, beta, it == 0, wk.r[cur], wk.u[cur],
+        cgp_sweep<PD, PF, false, SKIP>(g, tm.rank, tm.size, MINSEG, s, cc, alpha, beta, it == 0, wk.r[cur], wk.u[cur],
                                  wk.p[cur], wk.r[cur ^ 1], wk.u[cur ^ 1], wk.p[cur ^ 1], x, pp[0], pp[1], pp[2]);
         if (!team_reduce_n<3>(tm, pp, wk.red, tt)) return -1;
         ++it;

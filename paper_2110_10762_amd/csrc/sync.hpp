@@ -147,7 +147,7 @@ template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWorkP &wk, double abs_thresh2) {
     static_assert(DIM == 2, "the preconditioned CG is two-dimensional");
-    return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_GPU>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+    return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_GPU, 4, true>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
 
 template <int DIM>
