@@ -32,7 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
-ASYNC_DEPTH = 8         # fine steps per pass inside the persistent asynchronous kernel (2D)
+ASYNC_DEPTH = 12        # fine steps per pass inside the persistent asynchronous kernel (2D)
 
 # Bytes per launch moved between L2 and the memory fabric, from two rocprofv3
 # --pmc runs (FETCH_SIZE scaled by 1.996, WRITE_SIZE by 1.000: the factors a

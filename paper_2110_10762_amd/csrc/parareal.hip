@@ -60,9 +60,10 @@ static const Shape kShapes2D[] = {{2, 32, 1},  {2, 32, 2},   {2, 32, 4},  {2, 32
                                   {2, 24, 12}, {2, 16, 16},  {1, 64, 8},  {2, 16, 4},  {2, 8, 4},
                                   {2, 128, 4}, {3, 128, 4},  {2, 128, 8}, {3, 128, 8}, {4, 128, 8},
                                   {3, 256, 8}, {2, 128, 16}, {3, 96, 8},  {2, 128, 1}, {3, 128, 12},
-                                  {2, SW_AUTO_ROWS, 8}, {2, 128, 12}, {2, SW_AUTO_ROWS, 12}};
+                                  {2, SW_AUTO_ROWS, 8}, {2, 128, 12}, {2, SW_AUTO_ROWS, 12},
+                                  {2, 128, 14}, {2, SW_AUTO_ROWS, 14}};
 static const Shape kShapes3D[] = {{2, 8, 1}, {2, 16, 1}, {1, 16, 1}, {2, 4, 1}};
-static const int kDefault2D = 22;        // sliding window (2, auto rows, 12): batches of states
+static const int kDefault2D = 24;        // sliding window (2, auto rows, 14): batches of states
 static const int kDefault2DSingle = 4;   // register strip (2, 16, 8): one state (more waves)
 static const int kDefault3D = 0;   // (2, 8, 1)
 static const int kNum2D = sizeof(kShapes2D) / sizeof(kShapes2D[0]);
@@ -312,6 +313,8 @@ static void launch2d_shape(int shape, hipStream_t st, const double *src, double 
         case 20: launch2d_sw<2, 8>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
         case 21:
         case 22: launch2d_sw<2, 12>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
+        case 23:
+        case 24: launch2d_sw<2, 14>(st, src, dst, ss, ds, n, r, steps, count, ry); return;
         default: break;
     }
     switch (shape) {
