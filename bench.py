@@ -35,14 +35,14 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 ASYNC_DEPTH = 12        # fine steps per pass inside the persistent asynchronous kernel (2D)
 
 # Bytes per launch moved between L2 and the memory fabric, from two rocprofv3
-# --pmc runs (FETCH_SIZE scaled by 1.996, WRITE_SIZE by 1.000: the factors a
+# --pmc runs (FETCH_SIZE scaled by 1.994, WRITE_SIZE by 1.000: the factors a
 # plain copy of known size gives), kept in profiles/.  They describe the
 # kernel sources whose code (comments aside) has this digest and are reported
 # as null once that code changes.
-PROFILED_SOURCES = "5941e905f3b0a1dc"
-PROFILED_TRAFFIC = {"async": 634.35 + 426.39,      # GB, one launch
-                    "fine": 0.4941 + 0.4793,       # GB, mean over the sync solve's passes
-                    "sweep": 27.672 + 20.701}      # GB, mean over the sync solve's sweeps
+PROFILED_SOURCES = "a7a622b78458e184"
+PROFILED_TRAFFIC = {"async": 612.08 + 389.50,      # GB, one launch
+                    "fine": 0.4954 + 0.4745,       # GB, mean over the sync solve's passes
+                    "sweep": 27.472 + 20.697}      # GB, mean over the sync solve's sweeps
 
 
 def sources_digest():
