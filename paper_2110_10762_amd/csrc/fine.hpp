@@ -509,4 +509,120 @@ __global__ __launch_bounds__(BLOCK) void k_fine3d(const double *__restrict__ src
     fine3d_strip<XP, R>(src + st * sstride, dst + st * dstride, n, r, sx, sy, z0, z1);
 }
 
+// Depth-D pass of a 3D state (temporal blocking along z): strip (sx, sy) of
+// W = 64 - 2D columns, one per lane (x-neighbours by DPP), and R rows, over
+// planes [z0, z1).  The wave marches up z one input plane at a time and
+// holds, for each level, the two most recent planes of the level below
+// (R + 2D rows of its column); level l + 1 forms plane k - l - 1 as soon as
+// plane k - l of level l exists, so level D reaches HBM D planes behind the
+// input.  Level l + 1 is formed on rows [l + 1, R + 2D - l - 1) of the lane's
+// column, the rows its successor reads; halo rows, columns and planes are
+// recomputed, not exchanged.  Planes, rows and columns outside the grid are
+// the odd extension, which every update keeps exactly, so the zero Dirichlet
+// values need no masks.  Levels at and beyond `steps` copy (coefficient 0).
+// Each point is formed as in k_fine3d, so the two kernels agree bit for bit.
+template <int R, int D, int PF>
+__device__ __forceinline__ void fine3d_tb_strip(const double *__restrict__ src, double *__restrict__ dst, int n,
+                                                double r, int steps, int sx, int sy, int z0, int z1) {
+    constexpr int Y = R + 2 * D;   // rows of the lane's column, halo included
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int x0 = sx * (WAVE - 2 * D) - D;
+    double xs;
+    const unsigned xo = (unsigned)reflect(x0 + lane, n, xs) * 8u;   // byte offset of the lane's column
+    const bool own = lane >= D && lane < WAVE - D && x0 + lane < n;
+    const int y0 = sy * R - D;
+    int yo[Y];   // reflected row offsets and signs (wave-uniform)
+    double ysg[Y];
+#pragma unroll
+    for (int j = 0; j < Y; ++j) yo[j] = reflect(y0 + j, n, ysg[j]) * n;
+    double rt[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) rt[t] = t < steps ? r : 0.0;
+    double w0[D][Y], w1[D][Y];   // level l: planes two and one behind its newest
+#pragma unroll
+    for (int l = 0; l < D; ++l)
+#pragma unroll
+        for (int j = 0; j < Y; ++j) w0[l][j] = w1[l][j] = 0.0;
+    const int nk = (z1 - z0) + 2 * D;   // input planes z0 - D .. z1 + D - 1
+    const int k0 = z0 - D;
+    const long long nn = (long long)n * n;
+    double ring[PF][Y], zsg[PF];
+    // row addresses are wave-uniform, the lane offset is 32-bit
+    auto issue = [&](int kk, double (&w)[Y], double &sg) {
+        const int zi = reflect(kk, n, sg);
+        const double *pl = src + zi * nn;
+#pragma unroll
+        for (int j = 0; j < Y; ++j) w[j] = *reinterpret_cast<const double *>(reinterpret_cast<const char *>(pl + yo[j]) + xo);
+    };
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        zsg[q] = 0.0;
+#pragma unroll
+        for (int j = 0; j < Y; ++j) ring[q][j] = 0.0;
+        if (q < nk) issue(k0 + q, ring[q], zsg[q]);
+    }
+    for (int kb = 0; kb < nk; kb += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int t = kb + q;
+            if (t >= nk) break;
+            double c[Y];
+#pragma unroll
+            for (int j = 0; j < Y; ++j) c[j] = (zsg[q] * ysg[j] * xs) * ring[q][j];
+            if (t + PF < nk) issue(k0 + t + PF, ring[q], zsg[q]);
+            // level l + 1 at plane k - l - 1, row by row in place: row j
+            // needs rows j - 1 .. j + 1 of the older plane of level l, so the
+            // row below is kept in `below` once its slot has moved on
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+                double below = w1[l][l];
+                w0[l][l] = w1[l][l];
+                w1[l][l] = c[l];
+#pragma unroll
+                for (int j = l + 1; j < Y - l - 1; ++j) {
+                    const double cur = w1[l][j];
+                    const double lr = from_lower_lane(cur) + from_upper_lane(cur);
+                    const double s2 = (below + w1[l][j + 1]) + (w0[l][j] + c[j]);
+                    const double v = euler_update(cur, lr, s2, 6.0, rt[l]);
+                    w0[l][j] = cur;
+                    w1[l][j] = c[j];
+                    c[j] = v;
+                    below = cur;
+                }
+                w0[l][Y - l - 1] = w1[l][Y - l - 1];
+                w1[l][Y - l - 1] = c[Y - l - 1];
+            }
+            const int z = k0 + t - D;
+            if (z >= z0 && z < z1 && own) {
+                double *pl = dst + z * nn;
+                const int x = x0 + lane;
+#pragma unroll
+                for (int j = D; j < Y - D; ++j)
+                    if (y0 + j < n) (pl + (long long)(y0 + j) * n)[x] = c[j];
+            }
+        }
+    }
+}
+
+// PF: input planes in flight ahead of the march.
+template <int R, int D, int PF>
+__global__ __launch_bounds__(BLOCK) void k_fine3d_tb(const double *__restrict__ src, double *__restrict__ dst,
+                                                     long long sstride, long long dstride, int n, double r,
+                                                     int steps, int nsx, int nsy, int nsz, int zc, int count,
+                                                     int nblk) {
+    const int L = xcd_remap(blockIdx.x, nblk);
+    if (L >= nblk) return;
+    const long long wv = (long long)L * WAVES_PER_BLOCK + wave_id();
+    const long long per_state = (long long)nsx * nsy * nsz;
+    if (wv >= per_state * count) return;
+    const int st = (int)(wv / per_state);
+    int rem = (int)(wv - (long long)st * per_state);
+    const int sx = rem % nsx;   // strips of the same rows side by side
+    rem /= nsx;
+    const int sy = rem % nsy;
+    const int sz = rem / nsy;
+    const int z0 = sz * zc;
+    fine3d_tb_strip<R, D, PF>(src + st * sstride, dst + st * dstride, n, r, steps, sx, sy, z0, min(n, z0 + zc));
+}
+
 }  // namespace pr

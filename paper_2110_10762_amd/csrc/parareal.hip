@@ -62,10 +62,13 @@ static const Shape kShapes2D[] = {{2, 32, 1},  {2, 32, 2},   {2, 32, 4},  {2, 32
                                   {3, 256, 8}, {2, 128, 16}, {3, 96, 8},  {2, 128, 1}, {3, 128, 12},
                                   {2, SW_AUTO_ROWS, 8}, {2, 128, 12}, {2, SW_AUTO_ROWS, 12},
                                   {2, 128, 14}, {2, SW_AUTO_ROWS, 14}};
-static const Shape kShapes3D[] = {{2, 8, 1}, {2, 16, 1}, {1, 16, 1}, {2, 4, 1}};
+// 3D: (x points per lane, rows, depth); depth > 1 marches z with that many
+// time levels (k_fine3d_tb), depth 1 is the one-step register strip.
+static const Shape kShapes3D[] = {{2, 8, 1}, {2, 16, 1}, {1, 16, 1}, {2, 4, 1}, {1, 8, 2}, {1, 6, 3}, {1, 8, 4}};
 static const int kDefault2D = 24;        // sliding window (2, auto rows, 14): batches of states
 static const int kDefault2DSingle = 4;   // register strip (2, 16, 8): one state (more waves)
-static const int kDefault3D = 0;   // (2, 8, 1)
+static const int kDefault3D = 0;     // (2, 8, 1): one step per slice
+static const int kDefault3DTB = 6;   // (1, 8, 4): slices of several steps
 static const int kNum2D = sizeof(kShapes2D) / sizeof(kShapes2D[0]);
 static const int kNum3D = sizeof(kShapes3D) / sizeof(kShapes3D[0]);
 
@@ -74,7 +77,7 @@ static int find_shape(int dim, int d, int r, int xp) {
     const Shape *tab = dim == 2 ? kShapes2D : kShapes3D;
     const int cnt = dim == 2 ? kNum2D : (dim == 3 ? kNum3D : 0);
     for (int i = 0; i < cnt; ++i)
-        if ((d <= 0 || (dim == 2 ? tab[i].d : 1) == d) && (r <= 0 || tab[i].r == r) && (xp <= 0 || tab[i].xp == xp))
+        if ((d <= 0 || tab[i].d == d) && (r <= 0 || tab[i].r == r) && (xp <= 0 || tab[i].xp == xp))
             return i;
     return -1;
 }
@@ -225,7 +228,7 @@ static int derive(const pr_config &c, Prob &P) {
     P.cg_maxit = c.cg_maxit > 0 ? c.cg_maxit : 10 * c.n + 100;
     P.kmax = (c.kmax <= 0 || c.kmax > c.nslices) ? c.nslices : c.kmax;
     P.eps = c.eps;
-    P.shape = P.dim == 2 ? kDefault2D : (P.dim == 3 ? kDefault3D : 0);
+    P.shape = P.dim == 2 ? kDefault2D : (P.dim == 3 ? (P.m > 1 ? kDefault3DTB : kDefault3D) : 0);
     P.shape1 = P.dim == 2 ? kDefault2DSingle : -1;
     if (P.dim > 1 && (c.tb_depth > 0 || c.tile_rows > 0 || c.fine_xpts > 0)) {
         P.shape1 = -1;
@@ -347,8 +350,58 @@ static void launch3d(hipStream_t st, const double *src, double *dst, long long s
                        nsz, zc, count, nblk);
 }
 
+// Planes per z segment of a depth-D pass: the segment count whose units fill
+// the GPU's wave slots in whole rounds at the least marched planes (each
+// segment recomputes 2D halo planes).
+template <int R, int D, int PF>
+static int tb3_planes(int n, long long strips) {
+    static int slots = 0;
+    if (slots == 0) {
+        int occ = 0, ncu = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_fine3d_tb<R, D, PF>, BLOCK, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return n;
+        }
+        slots = std::max(1, occ * ncu * WAVES_PER_BLOCK);
+    }
+    int best = n;
+    double best_cost = 1e300;
+    for (int nseg = 1; nseg <= std::max(1, n / 8); ++nseg) {
+        const int zc = (n + nseg - 1) / nseg;
+        const long long units = strips * ((n + zc - 1) / zc);
+        const double cost = (double)((units + slots - 1) / slots) * (zc + 2 * D);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = zc;
+        }
+    }
+    return best;
+}
+
+template <int R, int D, int PF>
+static void launch3d_tb(hipStream_t st, const double *src, double *dst, long long ss, long long ds, int n,
+                        double r, int steps, int count) {
+    const int nsx = (n + WAVE - 2 * D - 1) / (WAVE - 2 * D), nsy = (n + R - 1) / R;
+    const int zc = tb3_planes<R, D, PF>(n, (long long)nsx * nsy * count);
+    const int nsz = (n + zc - 1) / zc;
+    const long long waves = (long long)nsx * nsy * nsz * count;
+    const int nblk = (int)((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
+    const int grid = 8 * ((nblk + 7) / 8);
+    hipLaunchKernelGGL((k_fine3d_tb<R, D, PF>), dim3(grid), dim3(BLOCK), 0, st, src, dst, ss, ds, n, r, steps, nsx,
+                       nsy, nsz, zc, count, nblk);
+}
+
 static void launch3d_shape(int shape, hipStream_t st, const double *src, double *dst, long long ss,
-                           long long ds, int n, double r, int count) {
+                           long long ds, int n, double r, int steps, int count) {
+    switch (shape) {
+        case 4: launch3d_tb<8, 2, 2>(st, src, dst, ss, ds, n, r, steps, count); return;
+        case 5: launch3d_tb<6, 3, 2>(st, src, dst, ss, ds, n, r, steps, count); return;
+        case 6: launch3d_tb<8, 4, 1>(st, src, dst, ss, ds, n, r, steps, count); return;
+        default: break;
+    }
     switch (shape) {
         case 0: launch3d<2, 8>(st, src, dst, ss, ds, n, r, count); break;
         case 1: launch3d<2, 16>(st, src, dst, ss, ds, n, r, count); break;
@@ -375,7 +428,7 @@ static void launch1d(hipStream_t st, const double *src, double *dst, long long s
 static int fine_depth(const Prob &P) {
     if (P.dim == 1) return 1 << 30;
     if (P.dim == 2) return kShapes2D[P.shape].d;
-    return 1;
+    return kShapes3D[P.shape].d;
 }
 
 // Passes of at most D steps; the passes ping-pong between dst and tmp so that
@@ -398,7 +451,7 @@ static int run_fine(pr_problem *h, const Prob &P, const double *src, double *dst
         const int d1 = kShapes2D[P.shape1].d;
         if ((steps + d1 - 1) / d1 <= 1 || tmp) shape = P.shape1;
     }
-    const int D = P.dim == 2 ? kShapes2D[shape].d : 1;
+    const int D = P.dim == 2 ? kShapes2D[shape].d : kShapes3D[shape].d;
     const int passes = (steps + D - 1) / D;
     if (passes > 1 && !tmp) return fail(PR_EINVAL, "internal: fine pass needs a scratch buffer");
     const double *cur = src;
@@ -410,7 +463,7 @@ static int run_fine(pr_problem *h, const Prob &P, const double *src, double *dst
         if (P.dim == 2)
             launch2d_shape(shape, h->stream, cur, tgt, cs, ts, P.n, P.r, st, count);
         else
-            launch3d_shape(shape, h->stream, cur, tgt, cs, ts, P.n, P.r, count);
+            launch3d_shape(shape, h->stream, cur, tgt, cs, ts, P.n, P.r, st, count);
         HIPCHK(hipGetLastError());
         cur = tgt;
         cs = ts;
@@ -720,7 +773,7 @@ extern "C" int pr_get_info(const pr_problem *h, int problem, pr_info *out) {
         out->xpts = kShapes2D[P.shape].xp;
         out->sliding = kShapes2D[P.shape].sliding() ? 1 : 0;
     } else if (P.dim == 3) {
-        out->tb_depth = 1;
+        out->tb_depth = kShapes3D[P.shape].d;
         out->tile_rows = kShapes3D[P.shape].r;
         out->xpts = kShapes3D[P.shape].xp;
     } else {
@@ -742,7 +795,7 @@ extern "C" int pr_fine_shape_get(int dim, int index, int *tb_depth, int *tile_ro
         return PR_OK;
     }
     if (dim == 3 && index >= 0 && index < kNum3D) {
-        if (tb_depth) *tb_depth = 1;
+        if (tb_depth) *tb_depth = kShapes3D[index].d;
         if (tile_rows) *tile_rows = kShapes3D[index].r;
         if (xpts) *xpts = kShapes3D[index].xp;
         if (sliding) *sliding = 0;

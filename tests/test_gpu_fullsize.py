@@ -176,3 +176,47 @@ def test_heat3d_full_async_then_sync_vs_fixed_point():
         prob.close()
         del lam, filler
         torch.cuda.empty_cache()
+
+
+@pytest.mark.gpu
+def test_heat3d_long_slices_sync_and_async_vs_modal_oracle():
+    # 128^3, N = 64 slices of m = 100 fine steps (the paper's regime of long
+    # slices, Section 5.1): G is a backward-Euler step with s = 7.5.  Sync at
+    # the GPU's k against the exact-G iterate and the fixed point; async
+    # (free) against the fixed point, at sampled slices.
+    p = workloads.heat3d_long()
+    d = disc_of(p)
+    N = d.nslices
+    assert d.m == 100
+    sample = [1, N // 2, N]
+    star = spectral.serial_fine(p.u0, d.r, d.m, N, slices=sample)
+    prob = pr.Problem(pr.config_of(p, eps=1e-10))
+    prob.set_async_options(mode=pr.PR_ASYNC_FREE, time_limit_s=120.0)
+    u0 = dev(p.u0)
+    lam = torch.empty((N + 1,) + p.u0.shape, dtype=torch.float64, device=DEV)
+    try:
+        print(f"heat3d_long 128^3 N={N} m={d.m}: sync solve", flush=True)
+        st = pr.Stats(N, N + 1)
+        prob.solve_sync(u0, lam, st)
+        assert st.converged == 1
+        k = st.iters
+        want = spectral.parareal_sync(p.u0, d.r, d.m, d.s, k, sample)
+        for j, i in enumerate(sample):
+            g = lam[i].cpu().numpy()
+            e = rel(g, want[j])
+            print(f"  sync k={k} slice {i}: err vs exact-G iterate {e:.2e}, vs fixed point "
+                  f"{rel(g, star[j]):.2e}", flush=True)
+            assert e <= TOL, i
+            assert rel(g, star[j]) <= TOL, i
+        print(f"heat3d_long 128^3 N={N}: async (free) solve", flush=True)
+        st = pr.Stats(N)
+        prob.solve_async(u0, lam, st)
+        assert st.converged == 1
+        for j, i in enumerate(sample):
+            e = rel(lam[i].cpu().numpy(), star[j])
+            print(f"  async kappa={st.kappa} slice {i}: err {e:.2e}", flush=True)
+            assert e <= TOL, i
+    finally:
+        prob.close()
+        del lam
+        torch.cuda.empty_cache()

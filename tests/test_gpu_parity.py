@@ -77,6 +77,31 @@ def test_fine_2d_all_shapes_bitwise_and_vs_oracle(n):
             assert np.array_equal(got, ref_bits), (d, rows, xp)
 
 
+def test_fine_3d_depth_shapes_wide():
+    # the z-marching kernels of depth 2-4 at a size of several x strips (n =
+    # 130 > 64 - 2D), y strips and z segments, with a step count no depth
+    # divides: against the oracle and bit for bit against one step per pass
+    n, steps = 130, 9
+    rng = np.random.default_rng(17)
+    x = states(rng, 2, (n, n, n))
+    prob = pr.Problem(pr.make_config(3, n, 0.5, 1.0, 2, 0.15 / (n + 1) ** 2))
+    r = prob.info().r
+    want = [heat.fine(x[c], r, steps) for c in range(2)]
+    outs = {}
+    for (d, rows, xp, sw) in pr.fine_shapes(3):
+        prob.set_fine_shape(d, rows, xp)
+        y = torch.empty_like(dev(x))
+        prob.apply_fine(dev(x), y, 2, steps)
+        outs[(d, rows, xp)] = y.cpu().numpy()
+    depths = sorted({k[0] for k in outs})
+    assert depths[0] == 1 and depths[-1] >= 4
+    ref = outs[[k for k in outs if k[0] == 1][0]]
+    for k, got in outs.items():
+        for c in range(2):
+            assert rel(got[c], want[c]) <= 1e-12, k
+        assert np.array_equal(got, ref), k
+
+
 @pytest.mark.parametrize("n", [31, 40, 2])
 def test_fine_3d_all_shapes(n):
     rng = np.random.default_rng(3 + n)

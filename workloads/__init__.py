@@ -19,6 +19,10 @@ Draw order per workload (NumPy PCG64, ``default_rng(seed)``):
                    sine-mode amplitudes (k_x, k_y <= 16, a = z / sqrt(kx^2+ky^2))
   adjoint  seed 4: u0 centres/widths (16 bumps), then target centres/widths
                    (8 bumps, amplitude 0.5)
+  heat3d_long seed 5: as heat3d (32 bumps + noise) on 128^3, 64 slices of 100
+                   fine steps each: the paper's regime of a slice 100 fine
+                   steps long (Section 5.1), which the 256^3 workload, with
+                   less than one step per slice, does not reach
 A Gaussian bump is exp(-|x - c|^2 / (2 sigma^2)) with amplitude 1; bumps near a
 wall are simply cut by the zero boundary.
 """
@@ -32,7 +36,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "grid", "bumps", "sine_modes_1d", "sine_modes_2d",
-    "heat1d", "heat2d", "heat3d", "adjoint2d", "batched", "by_name",
+    "heat1d", "heat2d", "heat3d", "heat3d_long", "adjoint2d", "batched", "by_name",
 ]
 
 
@@ -128,6 +132,21 @@ def heat3d(n: int = 256, nslices: int = 128, T: float = 2e-4) -> Problem:
     return p
 
 
+HEAT3D_LONG_STEPS = 100   # fine steps per slice, dt = 0.15 h^2
+
+
+def heat3d_long(n: int = 128, nslices: int = 64, steps: int = HEAT3D_LONG_STEPS) -> Problem:
+    rng = np.random.default_rng(5)
+    centres = rng.uniform(0.1, 0.9, (32, 3))
+    widths = rng.uniform(0.02, 0.1, 32)
+    noise = rng.normal(0.0, 0.01, n ** 3)
+    h = 1.0 / (n + 1)
+    dt = 0.15 * h * h
+    p = Problem("heat3d_long", 3, n, 0.5, nslices * steps * dt, nslices, dt)
+    p.u0 = bumps(n, 3, centres, widths) + noise.reshape(n, n, n)
+    return p
+
+
 def adjoint2d(n: int = 512, nslices: int = 32, T: float = 5e-3) -> Problem:
     rng = np.random.default_rng(4)
     c0 = rng.uniform(0.1, 0.9, (16, 2))
@@ -171,5 +190,5 @@ def batched(count: int = 512, sides: Tuple[int, ...] = BATCH_SIDES,
 
 
 def by_name(name: str) -> Problem:
-    return {"heat1d": heat1d, "heat2d": heat2d, "heat3d": heat3d,
+    return {"heat1d": heat1d, "heat2d": heat2d, "heat3d": heat3d, "heat3d_long": heat3d_long,
             "adjoint2d": adjoint2d}[name]()
