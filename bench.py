@@ -15,6 +15,7 @@ is reported beside it.
 
 Untimed extras (outside the timed region, skipped with --no-extras): the 2D
 fine sweep at every sliding-window depth D, the 3D workload (256^3, 128
+slices), a supplementary 3D case with slices of 100 fine steps (128^3, 64
 slices), the 512-problem batch (hipGraph, autotuned fine kernel) and the
 adjoint gradient (512^2, 32 slices), each compared at sampled outputs with the
 library's own serial fine integration (their agreement with the oracle is
@@ -251,7 +252,9 @@ def run_extras(dev):
              "rel_err_vs_gpu_serial_fine": (got - ser).abs().max().item() / sref}
         if drv == "sync":
             r["fine_ms"], r["coarse_ms"] = st.fine_ms, st.coarse_ms
-            c_bytes = (st.cg_iters * 64.0 + st.g_solves * 24.0 + (st.g_solves + st.g_skipped) * 48.0) * npts
+            # set-up 24 B from x0 = b (initial sweep), 32 from the last coarse value
+            c_bytes = (st.cg_iters * 64.0 + N * 24.0 + (st.g_solves - N) * 32.0
+                       + (st.g_solves + st.g_skipped) * 48.0) * npts
             r["roofline_sweep"] = {"kernel": "k_sweep_cg<3>", "bound": "hbm",
                                    "achieved": c_bytes / (st.coarse_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": c_bytes / (st.coarse_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
@@ -265,6 +268,56 @@ def run_extras(dev):
     out["heat3d"] = res
     prob.close()
     del lam, xs, ser, u0
+    torch.cuda.empty_cache()
+
+    # ---- 3D with long slices: 128^3, 64 slices of 100 fine steps (the paper's
+    # ratio of slice length to fine step), labelled apart from the 256^3 workload
+    p = workloads.heat3d_long()
+    N = p.nslices
+    prob = pr.Problem(pr.config_of(p, eps=1e-10))
+    prob.set_async_options(mode=pr.PR_ASYNC_FREE, time_limit_s=200.0)
+    info = prob.info()
+    u0 = torch.from_numpy(p.u0).to(dev)
+    lam = torch.empty((N + 1,) + p.u0.shape, dtype=torch.float64, device=dev)
+    sample = [1, N // 2, N]
+    st = pr.Stats()
+    prob.solve_fine(u0, lam, st)
+    ser_ms = st.wall_ms
+    ser = torch.stack([lam[i].clone() for i in sample])
+    sref = ser.abs().max().item()
+    npts = p.n ** 3
+    xs = lam[:N].clone()
+    ys = torch.empty_like(xs)
+    prob.apply_fine(xs, ys, N, info.m)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    prob.apply_fine(xs, ys, N, info.m)
+    torch.cuda.synchronize()
+    sweep_ms = (time.perf_counter() - t) * 1e3
+    del xs, ys
+    res = {"workload": "heat3d_long n=128^3 N=64 nu=0.5 dt=0.15h^2, 100 fine steps per slice (s = 7.5), CG 1e-12",
+           "label": "supplementary: the paper's slice of 100 fine steps; not one of the benchmark's configurations",
+           "serial_fine_ms": ser_ms,
+           "fine_sweep": {"kernel": f"k_fine3d_tb (depth {info.tb_depth}, rows {info.tile_rows})", "ms": sweep_ms,
+                          "glups": N * info.m * npts / (sweep_ms * 1e-3) / 1e9,
+                          "hbm_frac": N * -(-info.m // info.tb_depth) * 16.0 * npts / (sweep_ms * 1e-3) / 1e9
+                          / HBM_PEAK_GBS}}
+    for drv in ("sync", "async"):
+        st = pr.Stats(N, N + 1) if drv == "sync" else pr.Stats(N)
+        (prob.solve_sync if drv == "sync" else prob.solve_async)(u0, lam, st)
+        got = torch.stack([lam[i] for i in sample])
+        r = {"ms": st.wall_ms, "iters": st.iters, "cg_iters": st.cg_iters,
+             "rel_err_vs_gpu_serial_fine": (got - ser).abs().max().item() / sref}
+        if drv == "sync":
+            r["fine_ms"], r["coarse_ms"] = st.fine_ms, st.coarse_ms
+            r["C_F_ms"] = sweep_ms / N
+            r["C_G_ms"] = st.coarse_ms / max(1, st.g_solves)
+        else:
+            r["kappa"], r["teams"] = st.kappa, st.teams
+        res[drv] = r
+    out["heat3d_long"] = res
+    prob.close()
+    del lam, ser, u0
     torch.cuda.empty_cache()
 
     # ---- batched: 512 independent 2D problems, hipGraph, autotuned fine kernel
@@ -451,14 +504,15 @@ def main():
     # ---- roofline objects (algorithmic bytes per launch / live event durations)
     # Algorithmic bytes per point: F pass 16 (read + write the state).  2D
     # preconditioned CG (sync sweep and async teams): iteration 64 (reads r,
-    # u, p, x; writes the same four), set-up 40 (read b, write x, r0; read r0,
-    # write u0).  Unpreconditioned 2D CG (cg_precond = -1;
-    # products recomputed from r and p): iteration 48 (reads r, p_old, x;
-    # writes p, x, r'), set-up 24.  Correction 48 (read v, w_new, w_old,
-    # lambda_old, write lambda, w).
+    # u, p, x; writes the same four), set-up 40 from x0 = b (read b, write x,
+    # r0; read r0, write u0) in the initial sweep, 48 from the last coarse
+    # value (read x0 and b, write x, r0; read r0, write u0) afterwards.
+    # Unpreconditioned 2D CG (cg_precond = -1; products recomputed from r and
+    # p): iteration 48 (reads r, p_old, x; writes p, x, r'), set-up 24.
+    # Correction 48 (read v, w_new, w_old, lambda_old, write lambda, w).
     D = info.tb_depth
     passes = -(-m // D)
-    cg_it_b, cg_set_b = (64.0, 40.0) if info.cg_precond else (48.0, 24.0)
+    cg_it_b, cg_set_b, cg_warm_b = (64.0, 40.0, 48.0) if info.cg_precond else (48.0, 24.0, 24.0)
     fine_kernel = fine_kernel_name(info)
     rl = {}
     if rec["sync"]:
@@ -471,7 +525,7 @@ def main():
                       "launches": f_launches, "avg_launch_ms": f_ms / f_launches,
                       "glups": sum(x["fine_lups"] for x in s) / (f_ms * 1e-3) / 1e9}
         c_ms = sum(x["coarse_ms"] for x in s)
-        c_bytes = sum(x["cg_iters"] * cg_it_b * npts + x["g_solves"] * cg_set_b * npts
+        c_bytes = sum(x["cg_iters"] * cg_it_b * npts + (N * cg_set_b + (x["g_solves"] - N) * cg_warm_b) * npts
                       + (x["g_solves"] + x["g_skipped"]) * 48.0 * npts for x in s)
         c_launches = sum(x["iters"] + 1 for x in s)
         rl["sweep"] = {"kernel": "k_sweep_cg<2,true>" if info.cg_precond else "k_sweep_cg<2,false>", "bound": "hbm", "achieved": c_bytes / (c_ms * 1e-3) / 1e9,
@@ -487,7 +541,7 @@ def main():
             solves = x["g_solves"] - N          # minus the initial coarse sweep
             # per update: F passes, predecessor copy 16, correction + next slot 48
             a_bytes += (upd * (a_passes * 16.0 + 16.0 + 48.0) + x["kernel_cg_iters"] * cg_it_b
-                        + solves * cg_set_b) * npts
+                        + solves * cg_warm_b) * npts
         rl["async"] = {"kernel": f"k_async<2,2,0,{ASYNC_DEPTH},false,{'true' if info.cg_precond else 'false'}>",
                        "bound": "hbm",
                        "achieved": a_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",

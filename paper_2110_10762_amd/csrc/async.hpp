@@ -330,7 +330,7 @@ __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const do
 // ---- coarse solve of one state by a team; returns iterations or -1
 template <int DIM, int RR, bool PCG>
 __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double *x, const CGWork &wk,
-                           const CGWork2 &wk2, double abs_thresh2 = -1.0) {
+                           const CGWork2 &wk2, double abs_thresh2 = -1.0, const double *xg = nullptr) {
     if constexpr (DIM == 1) {
         if (wave_id() == 0) {
             double v[RR], inv[RR];
@@ -363,11 +363,11 @@ __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double
             const long long o = (long long)a.team_of[blockIdx.x] * a.cgs;
             const CGWorkP wkp{{wk2.r[0], wk2.r[1]}, {a.cgw0 + o, a.cgw1 + o}, {wk2.p[0], wk2.p[1]}, wk2.red};
             it = cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_TEAM, 1>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wkp,
-                                                           abs_thresh2);
+                                                           abs_thresh2, xg);
         } else if constexpr (DIM == 2)
             it = cg_team_2d_r<true>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk2, abs_thresh2);
         else
-            it = cg_team_dim<DIM, 4, DIM == 3>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2);
+            it = cg_team_dim<DIM, 4, DIM == 3>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, b, x, wk, abs_thresh2, xg);
         if (it < 0) return -1;
         return team_sync(tm) ? it : -1;
     }
@@ -613,8 +613,9 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                     if (!team_reduce<false>(tm, nrm_part, wk.red, nrm, lds)) goto out;
                     thr = a.cg_tol * a.cg_tol * nrm;
                 }
+                // the literal form starts from the last coarse value G(x_old)
                 const int it = team_coarse<DIM, RR, PCG>(tm, a, a.incr ? dbuf : x_new, a.incr ? ybuf : w_new, wk, wk2,
-                                                         thr);
+                                                         thr, a.incr ? nullptr : w_old);
                 if (it < 0) goto out;
                 cg_its += (unsigned long long)it;
                 ++g_solves;

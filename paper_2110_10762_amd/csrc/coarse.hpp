@@ -293,9 +293,11 @@ __device__ __forceinline__ double cpt_apply(const CPt &q, const double (&v)[2 * 
 // operand v and the stores per mode:
 //   CG3_A: v = r + beta p_old (r when `first`); p = v, sum v.(A v);
 //   CG3_B: v = p; x += alpha v, r -= alpha A v (in place), sum r.r;
-//   CG3_S: v = b (set-up with x0 = b); x = b, r = b - A b, sums r.r and b.b.
+//   CG3_S: v = b (set-up with x0 = b); x = b, r = b - A b, sums r.r and b.b;
+//   CG3_W: v = x0, a given guess (set-up); x = x0, r = b - A x0 with b (vb)
+//          read at the output point, sums r.r and b.b.
 // A v is formed exactly as in the chunk-wise phases (cpt_apply's order).
-enum { CG3_A = 0, CG3_B = 1, CG3_S = 2 };
+enum { CG3_A = 0, CG3_B = 1, CG3_S = 2, CG3_W = 3 };
 
 struct SW3Row {    // raw loads for one step: centre row (with the strip-border
                    // point) and the two side rows, of one or two vectors
@@ -332,6 +334,7 @@ __device__ __forceinline__ void sw3_issue(const double *__restrict__ va, const d
         w.xo = x[io];
         w.ro = r[io];
     }
+    if constexpr (MODE == CG3_W) w.ro = vb[(yok && lv) ? ob : 0];   // b at the output point
 }
 
 template <int MODE, int PF>
@@ -409,12 +412,18 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
                             const double rv = __builtin_fma(-coef, av, w.ro);
                             r[i] = rv;
                             acc0 = __builtin_fma(rv, rv, acc0);
-                        } else {
+                        } else if constexpr (MODE == CG3_S) {
                             const double rv = vm1c - av;
                             x[i] = vm1c;
                             r[i] = rv;
                             acc0 = __builtin_fma(rv, rv, acc0);
                             acc1 = __builtin_fma(vm1c, vm1c, acc1);
+                        } else {
+                            const double rv = w.ro - av;
+                            x[i] = vm1c;
+                            r[i] = rv;
+                            acc0 = __builtin_fma(rv, rv, acc0);
+                            acc1 = __builtin_fma(w.ro, w.ro, acc1);
                         }
                     }
                 }
@@ -433,8 +442,9 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
 // the iteration count, or -1 if the launch was aborted.  x and b must not
 // alias.  All lanes of a wave run every chunk (lanes past the row end carry
 // zeros) so that the lane shifts see the whole chunk.
-//   abs_thresh2 < 0: x0 = b, stop at ||r||^2 <= tol^2 ||b||^2 (the coarse
-//                    propagator applied to a state);
+//   abs_thresh2 < 0: x0 = b (or the guess xg, marching 3D set-up only), stop
+//                    at ||r||^2 <= tol^2 ||b||^2 (the coarse propagator
+//                    applied to a state);
 //   abs_thresh2 >= 0: x0 = 0, stop at ||r||^2 <= abs_thresh2 (applied to the
 //                    change of a state: a zero right-hand side returns 0).
 // Per iteration: phase A forms p = r + beta p_old (recomputed at the
@@ -446,7 +456,7 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
 template <int DIM, int U, bool SW3 = false>
 __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int maxit,
                            const double *__restrict__ b, double *__restrict__ x, const CGWork &wk,
-                           double abs_thresh2) {
+                           double abs_thresh2, const double *__restrict__ xg = nullptr) {
     static_assert(!SW3 || DIM == 3, "the marching phases are three-dimensional");
     constexpr int V = 2 * DIM;
     __shared__ double lds[MAX_WAVES];
@@ -459,7 +469,9 @@ __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int ma
     const bool from_zero = abs_thresh2 >= 0.0;
 
     double rr_p = 0.0, bb_p = 0.0, unused = 0.0;
-    if (SW3 && !from_zero)
+    if (SW3 && !from_zero && xg)
+        cg3_sweep_sw<CG3_W, 4>(g, tm.rank, tm.size, s, 0.0, true, xg, b, x, r, nullptr, rr_p, bb_p);
+    else if (SW3 && !from_zero)
         cg3_sweep_sw<CG3_S, 4>(g, tm.rank, tm.size, s, 0.0, true, b, nullptr, x, r, nullptr, rr_p, bb_p);
     else
     for (long long c0 = cr.begin + w; c0 < cr.end; c0 += U * nw) {

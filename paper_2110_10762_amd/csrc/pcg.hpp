@@ -89,20 +89,22 @@ __device__ __forceinline__ Cheb<PD> cheb_coef(double lo, double hi) {
     return c;
 }
 
-// Set-up: x0 (b or 0), r0 = b - A x0 and the partial sum of (b, b), chunk by
-// chunk over the team's chunk range.
+// Set-up: x0 (b, 0, or the given guess xg), r0 = b - A x0 and the partial
+// sum of (b, b), chunk by chunk over the team's chunk range.
 __device__ __forceinline__ void cgp_start(const Geom &g, const ChunkRange &cr, double s, bool from_zero,
-                                          const double *__restrict__ b, double *__restrict__ x,
-                                          double *__restrict__ r0, double &bb) {
+                                          const double *__restrict__ b, const double *__restrict__ xg,
+                                          double *__restrict__ x, double *__restrict__ r0, double &bb) {
     for (long long c = cr.begin + wave_id(); c < cr.end; c += nwaves()) {
         const CPt q = cpt_at(g, c);
         double v[4];
-        cpt_load<2>(q, g.n, [&](int j) { return b[j]; }, v);
-        double bc;
-        const double ab = cpt_apply<2>(q, v, bc, 4.0, s);
+        const double *op = xg ? xg : b;   // the stencil operand: x0
+        cpt_load<2>(q, g.n, [&](int j) { return op[j]; }, v);
+        double oc;
+        const double ao = cpt_apply<2>(q, v, oc, 4.0, s);
         if (q.m & CP_VALID) {
-            x[q.c] = from_zero ? 0.0 : bc;
-            r0[q.c] = from_zero ? bc : bc - ab;
+            const double bc = xg ? b[q.c] : oc;
+            x[q.c] = from_zero ? 0.0 : oc;
+            r0[q.c] = from_zero ? bc : bc - ao;
             bb = __builtin_fma(bc, bc, bb);
         }
     }
@@ -273,19 +275,21 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
 }
 
 // Solves (I - s h^2 L_h) x = b in 2D by the preconditioned CG above; same
-// start and stop rules as cg_team_dim (abs_thresh2 < 0: x0 = b, relative
-// stop; >= 0: x0 = 0, absolute stop).  Returns the iteration count, or -1 if
-// the launch was aborted.  x must not alias b or the work vectors.
+// start and stop rules as cg_team_dim (abs_thresh2 < 0: x0 = b, or the guess
+// xg when given, relative stop; >= 0: x0 = 0, absolute stop).  Returns the
+// iteration count, or -1 if the launch was aborted.  x must not alias b, xg
+// or the work vectors.
 template <int PD, int MINSEG, int PF = 4, bool SKIP = false>
 __device__ int cg_team_2d_p(Team &tm, const Geom &g, double s, double tol, int maxit,
                             const double *__restrict__ b, double *__restrict__ x, const CGWorkP &wk,
-                            double abs_thresh2) {
+                            double abs_thresh2, const double *__restrict__ xg = nullptr) {
     const bool from_zero = abs_thresh2 >= 0.0;
+    if (from_zero) xg = nullptr;
     const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
     // the spectrum of I - s h^2 L_h lies in (1, 1 + 8 s)
     const Cheb<PD> cc = cheb_coef<PD>(1.0, 1.0 + 8.0 * s);
     double bb = 0.0;
-    cgp_start(g, cr, s, from_zero, b, x, wk.r[0], bb);
+    cgp_start(g, cr, s, from_zero, b, xg, x, wk.r[0], bb);
     if (!team_sync(tm)) return -1;
     double part[4] = {0.0, 0.0, 0.0, bb}, tot[4];
     cgp_sweep<PD, PF, true, SKIP>(g, tm.rank, tm.size, MINSEG, s, cc, 0.0, 0.0, true, wk.r[0], nullptr, nullptr,

@@ -119,17 +119,19 @@ struct SweepBufs {
 
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
-                                       const double *b, double *x, const CGWork &wk, double abs_thresh2) {
+                                       const double *b, double *x, const CGWork &wk, double abs_thresh2,
+                                       const double *xg = nullptr) {
     // 3D whole-GPU sweep: marching phases (7.7 s for the 3D workload against
     // 8.7 s with two chunks per wave in flight and 9.0 s with one; the
     // one-synchronisation form with w and s stored moves 80 B per point and
     // took 10.9 s)
-    return cg_team_dim<DIM, 2, DIM == 3>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+    return cg_team_dim<DIM, 2, DIM == 3>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2, xg);
 }
 
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
-                                       const double *b, double *x, const CGWork2 &wk, double abs_thresh2) {
+                                       const double *b, double *x, const CGWork2 &wk, double abs_thresh2,
+                                       const double * = nullptr) {   // starts from b
     static_assert(DIM == 2, "the recomputing CG is two-dimensional");
     // the whole GPU has more waves than a state has rows per column strip:
     // every wave takes a few chunks (the marching sweep measured 1.6x slower)
@@ -138,23 +140,26 @@ __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double
 
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
-                                       const double *b, double *x, const CGWork2M &wk, double abs_thresh2) {
+                                       const double *b, double *x, const CGWork2M &wk, double abs_thresh2,
+                                       const double * = nullptr) {   // starts from b
     static_assert(DIM == 2, "the recomputing CG is two-dimensional");
     return cg_team_2d_r<true>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
 
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
-                                       const double *b, double *x, const CGWorkP &wk, double abs_thresh2) {
+                                       const double *b, double *x, const CGWorkP &wk, double abs_thresh2,
+                                       const double *xg = nullptr) {
     static_assert(DIM == 2, "the preconditioned CG is two-dimensional");
-    return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_GPU, 4, true>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+    return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_GPU, 4, true>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2, xg);
 }
 
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
-                                       const double *b, double *x, const CGWorkPT &wk, double abs_thresh2) {
+                                       const double *b, double *x, const CGWorkPT &wk, double abs_thresh2,
+                                       const double *xg = nullptr) {
     static_assert(DIM == 2, "the preconditioned CG is two-dimensional");
-    return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_TEAM, 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
+    return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_TEAM, 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2, xg);
 }
 
 template <int DIM, typename WK>
@@ -173,9 +178,13 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
         double *wi = B.w + (long long)i * npts;
         const double *vi = B.v + (long long)i * npts;
         if (!skip) {
-            // one call site: the kernel holds a single copy of the solver
+            // one call site: the kernel holds a single copy of the solver.  A
+            // solve of the literal form starts from the slice's last coarse
+            // value G(lambda_{i-1}^{k-1}): its residual is then the change of
+            // the input, small once the iteration settles (same stop rule)
             const int it = team_cg<DIM>(tm, g, s, tol, maxit, incr ? dprev : B.lam + (long long)(i - 1) * npts,
-                                        B.wn, wk, incr ? tol * tol * nrm_prev : -1.0);
+                                        B.wn, wk, incr ? tol * tol * nrm_prev : -1.0,
+                                        (init || incr) ? nullptr : wi);
             if (it < 0) return false;
             its += (unsigned long long)it;
         }
