@@ -504,15 +504,15 @@ def main():
     # ---- roofline objects (algorithmic bytes per launch / live event durations)
     # Algorithmic bytes per point: F pass 16 (read + write the state).  2D
     # preconditioned CG (sync sweep and async teams): iteration 64 (reads r,
-    # u, p, x; writes the same four), set-up 40 from x0 = b (read b, write x,
-    # r0; read r0, write u0) in the initial sweep, 48 from the last coarse
-    # value (read x0 and b, write x, r0; read r0, write u0) afterwards.
+    # u, p, x; writes the same four), set-up (one march) 32 from x0 = b (read
+    # b, write x, r0, u0) in the initial sweep, 40 from the last coarse value
+    # (read x0 and b, write x, r0, u0) afterwards.
     # Unpreconditioned 2D CG (cg_precond = -1; products recomputed from r and
     # p): iteration 48 (reads r, p_old, x; writes p, x, r'), set-up 24.
     # Correction 48 (read v, w_new, w_old, lambda_old, write lambda, w).
     D = info.tb_depth
     passes = -(-m // D)
-    cg_it_b, cg_set_b, cg_warm_b = (64.0, 40.0, 48.0) if info.cg_precond else (48.0, 24.0, 24.0)
+    cg_it_b, cg_set_b, cg_warm_b = (64.0, 32.0, 40.0) if info.cg_precond else (48.0, 24.0, 24.0)
     fine_kernel = fine_kernel_name(info)
     rl = {}
     if rec["sync"]:

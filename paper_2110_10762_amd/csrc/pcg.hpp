@@ -89,44 +89,26 @@ __device__ __forceinline__ Cheb<PD> cheb_coef(double lo, double hi) {
     return c;
 }
 
-// Set-up: x0 (b, 0, or the given guess xg), r0 = b - A x0 and the partial
-// sum of (b, b), chunk by chunk over the team's chunk range.
-__device__ __forceinline__ void cgp_start(const Geom &g, const ChunkRange &cr, double s, bool from_zero,
-                                          const double *__restrict__ b, const double *__restrict__ xg,
-                                          double *__restrict__ x, double *__restrict__ r0, double &bb) {
-    for (long long c = cr.begin + wave_id(); c < cr.end; c += nwaves()) {
-        const CPt q = cpt_at(g, c);
-        double v[4];
-        const double *op = xg ? xg : b;   // the stencil operand: x0
-        cpt_load<2>(q, g.n, [&](int j) { return op[j]; }, v);
-        double oc;
-        const double ao = cpt_apply<2>(q, v, oc, 4.0, s);
-        if (q.m & CP_VALID) {
-            const double bc = xg ? b[q.c] : oc;
-            x[q.c] = from_zero ? 0.0 : oc;
-            r0[q.c] = from_zero ? bc : bc - ao;
-            bb = __builtin_fma(bc, bc, bb);
-        }
-    }
-}
-
 // Raw loads of one march step: input row (r, u, p_old) and output row (x,
 // u, p_old).
 struct PRow {
     double r, u, p, x, uo, po;
 };
 
-// One iteration (or, SETUP, the first preconditioning u0 = p(A) r0 with
-// w0 = A u0, p taken as 0) of the team's share of the state; accumulates the
-// partial sums of (r', u'), (w', u') and (r', r') over the points the wave
-// owns.
+// One iteration of the team's share of the state; accumulates the partial
+// sums of (r', u'), (w', u') and (r', r') over the points the wave owns.
+// SETUP: the start of a solve in the same march, with rin = b, pin = x0 (b,
+// a guess, or null for x0 = 0) and alpha = 1: the first level forms
+// r0 = b - A x0, then u0 = p(A) r0 and w0 = A u0; x = x0 is written and
+// (b, b) summed into bb.
 template <int PD, int PF, bool SETUP, bool SKIP>
 __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int minseg, double s,
                                           const Cheb<PD> &cc, double alpha, double beta, bool first,
                                           const double *__restrict__ rin, const double *__restrict__ uin,
                                           const double *__restrict__ pin, double *__restrict__ rout,
                                           double *__restrict__ uout, double *__restrict__ pout,
-                                          double *__restrict__ x, double &ga, double &de, double &rr) {
+                                          double *__restrict__ x, double &ga, double &de, double &rr,
+                                          double &bb) {
     // Rounding exactly as written (no contraction of the remaining products
     // and sums into fused operations): a point's values come out the same
     // bits in every segment and strip that recomputes them, whatever code
@@ -143,7 +125,7 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
     const int seg = march_seg(n, nsx, waves, minseg);
     const int nseg = (n + seg - 1) / seg;
     const int units = nsx * nseg;
-    const bool read_p = !SETUP && !first;   // p_{-1} = 0
+    const bool read_p = SETUP ? pin != nullptr : !first;   // p_{-1} = 0; x0 = 0
     for (int un = wid; un < units; un += waves) {
         const int sx = un % nsx;   // strips of the same rows side by side
         const int ya = (un / nsx) * seg;
@@ -173,11 +155,15 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
             const int yi = reflect_row(kk, n, ys);
             const long long rb = (long long)yi * n;
             w.r = (rin + rb)[xi];
-            if constexpr (!SETUP) {
+            const int y = min(max(kk - H, ya), yb - 1);
+            const long long ob = (long long)y * n;
+            if constexpr (SETUP) {   // x0 at both rows, b at the output row
+                w.p = read_p ? (pin + rb)[xi] : 0.0;
+                w.x = read_p ? (pin + ob)[xi] : 0.0;
+                w.uo = (rin + ob)[xi];
+            } else {
                 w.u = (uin + rb)[xi];
                 w.p = read_p ? (pin + rb)[xi] : 0.0;
-                const int y = min(max(kk - H, ya), yb - 1);
-                const long long ob = (long long)y * n;
                 w.x = (x + ob)[xi];
                 w.uo = (uin + ob)[xi];
                 w.po = read_p ? (pin + ob)[xi] : 0.0;
@@ -202,10 +188,10 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
         auto step = [&](const int t, const int q) {
             const int k = k0 + t;
             const double sg = rsg[q];
-            // input row k: p_i (set-up: 0) and r_i
-            const double pn = SETUP ? 0.0 : __builtin_fma(beta, sg * ring[q].p, sg * ring[q].u);
+            // input row k: p_i (set-up: x0) and r_i (set-up: b)
+            const double pn = SETUP ? sg * ring[q].p : __builtin_fma(beta, sg * ring[q].p, sg * ring[q].u);
             const double rk = sg * ring[q].r;
-            // s_i = A p_i and r_{i+1} at row k - 1 (set-up: s = 0, alpha = 0: r0)
+            // s_i = A p_i and r_{i+1} at row k - 1 (set-up: r0 = b - A x0)
             double rn = 0.0;
             if (!SKIP || t >= 2) {
                 const double pl = from_lower_lane(pb), pr = from_upper_lane(pb);
@@ -248,12 +234,15 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
                 const int y = k - H;
                 if (y < yb && own) {
                     const long long i = (long long)y * n + xcol;
-                    if constexpr (!SETUP) {
+                    if constexpr (SETUP) {
+                        x[i] = ring[q].x;
+                        bb = __builtin_fma(ring[q].uo, ring[q].uo, bb);
+                    } else {
                         const double pi = __builtin_fma(beta, ring[q].po, ring[q].uo);
                         x[i] = __builtin_fma(alpha, pi, ring[q].x);
                         pout[i] = pi;
-                        rout[i] = rf;
                     }
+                    rout[i] = rf;
                     uout[i] = un;
                     ga = __builtin_fma(rf, un, ga);
                     de = __builtin_fma(wn, un, de);
@@ -285,15 +274,13 @@ __device__ int cg_team_2d_p(Team &tm, const Geom &g, double s, double tol, int m
                             double abs_thresh2, const double *__restrict__ xg = nullptr) {
     const bool from_zero = abs_thresh2 >= 0.0;
     if (from_zero) xg = nullptr;
-    const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
     // the spectrum of I - s h^2 L_h lies in (1, 1 + 8 s)
     const Cheb<PD> cc = cheb_coef<PD>(1.0, 1.0 + 8.0 * s);
-    double bb = 0.0;
-    cgp_start(g, cr, s, from_zero, b, xg, x, wk.r[0], bb);
-    if (!team_sync(tm)) return -1;
-    double part[4] = {0.0, 0.0, 0.0, bb}, tot[4];
-    cgp_sweep<PD, PF, true, SKIP>(g, tm.rank, tm.size, MINSEG, s, cc, 0.0, 0.0, true, wk.r[0], nullptr, nullptr,
-                            nullptr, wk.u[0], nullptr, x, part[0], part[1], part[2]);
+    // the start in one march: x = x0, r0 = b - A x0, u0 = p(A) r0, the sums
+    double part[4] = {0.0, 0.0, 0.0, 0.0}, tot[4];
+    cgp_sweep<PD, PF, true, SKIP>(g, tm.rank, tm.size, MINSEG, s, cc, 1.0, 0.0, true, b, nullptr,
+                                  from_zero ? nullptr : (xg ? xg : b), wk.r[0], wk.u[0], nullptr, x, part[0],
+                                  part[1], part[2], part[3]);
     if (!team_reduce_n<4>(tm, part, wk.red, tot)) return -1;
     double gamma = tot[0], rho = tot[2];
     const double thresh = from_zero ? (abs_thresh2 > 0.0 ? abs_thresh2 : tol * tol * tot[3]) : tol * tol * tot[3];
@@ -301,9 +288,10 @@ __device__ int cg_team_2d_p(Team &tm, const Geom &g, double s, double tol, int m
     int cur = 0;
     int it = 0;
     while (it < maxit && rho > thresh) {
-        double pp[3] = {0.0, 0.0, 0.0}, tt[3];
+        double pp[3] = {0.0, 0.0, 0.0}, tt[3], unused = 0.0;
         cgp_sweep<PD, PF, false, SKIP>(g, tm.rank, tm.size, MINSEG, s, cc, alpha, beta, it == 0, wk.r[cur], wk.u[cur],
-                                 wk.p[cur], wk.r[cur ^ 1], wk.u[cur ^ 1], wk.p[cur ^ 1], x, pp[0], pp[1], pp[2]);
+                                 wk.p[cur], wk.r[cur ^ 1], wk.u[cur ^ 1], wk.p[cur ^ 1], x, pp[0], pp[1], pp[2],
+                                 unused);
         if (!team_reduce_n<3>(tm, pp, wk.red, tt)) return -1;
         ++it;
         beta = tt[0] / gamma;
