@@ -72,6 +72,7 @@ struct SliceLoc {     // team-private control state of a slice (leader only)
     int reset_done;   // the injected reset has happened
     int zero_noted;   // idling: the zero change of the skipped update is recorded
     double last_sref; // predecessor drift at the version the last computed value's G read
+    int v_valid;      // v holds F(x_old) (2D explicit: F is batched per round)
 };
 
 struct AsyncWork {
@@ -327,6 +328,49 @@ __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const do
     }
 }
 
+// ---- 2D explicit F of several slices of the team's block at once: bit j of
+// `mask` is slice i0 + j * istep, bit j of `xo_mask` the x buffer holding its
+// x_old.  Each pass runs over every (slice, strip, segment) unit of the
+// team, so a pass costs one team barrier for all the slices, and the
+// segments are long (a single 1024^2 state on a quarter of the chip gets
+// 24-row segments that recompute as many halo rows).  Passes ping-pong
+// between v and the slice's scratch so that the last lands in v.
+template <int XP, int D>
+__device__ __forceinline__ bool team_fine_2d_batch(Team &tm, const AsyncArgs &a, int i0, int istep,
+                                                   unsigned long long mask, unsigned long long xo_mask) {
+    const int cnt = __popcll(mask);
+    if (cnt == 0) return true;
+    const int passes = (a.m + D - 1) / D;
+    const int waves = tm.size * nwaves();
+    const int wid = tm.rank * nwaves() + wave_id();
+    const long long np = a.npts, all = (long long)(a.N + 1) * np;
+    const int seg = march_seg(a.n, (long long)a.nsx * cnt, waves, 24);
+    const int nseg = (a.n + seg - 1) / seg;
+    const long long per = (long long)a.nsx * nseg;
+    const long long units = per * cnt;
+    for (int p = 0; p < passes; ++p) {
+        const int st = min(D, a.m - p * D);
+        const bool to_v = ((passes - 1 - p) % 2 == 0);
+        for (long long u = wid; u < units; u += waves) {
+            const int jj = (int)(u / per);   // the jj-th slice of the mask
+            const int rem = (int)(u - (long long)jj * per);
+            const int sx = rem % a.nsx;      // strips of the same rows side by side
+            const int sy = rem / a.nsx;
+            unsigned long long mm = mask;
+            for (int q = 0; q < jj; ++q) mm &= mm - 1;
+            const int j = __ffsll((long long)mm) - 1;
+            const int i = i0 + j * istep;
+            const double *src = p == 0 ? a.X + (long long)((xo_mask >> j) & 1) * all + i * np
+                                       : (to_v ? a.S : a.V) + i * np;
+            double *tgt = (to_v ? a.V : a.S) + i * np;
+            const int ya = sy * seg;
+            fine2d_sw<XP, D, 2, false>(src, tgt, a.n, a.r, st, sx, ya, min(a.n, ya + seg), sy & 1);
+        }
+        if (!team_sync(tm)) return false;
+    }
+    return true;
+}
+
 // ---- coarse solve of one state by a team; returns iterations or -1
 template <int DIM, int RR, bool PCG>
 __device__ int team_coarse(Team &tm, const AsyncArgs &a, const double *b, double *x, const CGWork &wk,
@@ -411,6 +455,35 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
         const int i_first = a.blocks ? 1 + (int)((long long)team * a.N / a.nteams) : team + 1;
         const int i_last = a.blocks ? (int)((long long)(team + 1) * a.N / a.nteams) : a.N;
         const int i_step = a.blocks ? 1 : a.nteams;
+        // 2D explicit: F of every live slice of the block whose v is not
+        // F(x_old) yet, batched at the start of the round (x_old of a slice
+        // changes only in its own update, so v stays valid through idle and
+        // stale updates)
+        constexpr bool FBATCH = DIM == 2 && !IMPL;
+        if constexpr (FBATCH) {
+            long long fb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (leader) {
+                unsigned long long m = 0, xm = 0;
+                for (int i = i_first, j = 0; i <= i_last && j < 64; i += i_step, ++j) {
+                    SliceLoc &L = a.loc[i];
+                    const bool live = !L.done && a.hdr[i].k < a.L &&
+                                      !(a.mode == AMODE_EXACT && a.hdr[i].final_from >= 0);
+                    if (live && !L.v_valid) {
+                        m |= 1ull << j;
+                        xm |= (unsigned long long)(L.xo & 1) << j;
+                        L.v_valid = 1;
+                    }
+                }
+                fb[0] = (long long)m;
+                fb[1] = (long long)xm;
+            }
+            if (!team_bcast(tm, bc, fb)) goto out;
+            tp = wall_clock64();
+            if (!team_fine_2d_batch<XP, D>(tm, a, i_first, i_step, (unsigned long long)fb[0],
+                                           (unsigned long long)fb[1]))
+                goto out;
+            t_fine += wall_clock64() - tp;
+        }
         for (int i = i_first; i <= i_last; i += i_step) {
             // ---------------- leader decides, team follows
             long long b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -471,6 +544,7 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                         L.f_final = (i == 1) ? 1 : 0;
                         L.stale_streak = 0;
                         L.last_sref = 0.0;   // version 0 of the predecessor
+                        L.v_valid = 0;
                         b[6] = 1;
                     }
                     pv = (i == 1) ? 0 : visible_version(a, i - 1);
@@ -505,6 +579,8 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                 b[3] = L.wo;
                 b[4] = myver;
                 b[5] = (pv == L.f_ver) ? 1 : 0;
+                b[7] = L.v_valid ? 0 : 1;   // F still to be computed for this update
+                if (action == ACT_UPDATE) L.v_valid = 1;
             }
             if (!team_bcast(tm, bc, b)) goto out;
             const int action = (int)b[0];
@@ -525,11 +601,16 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                 if (!a.incr) team_copy(tm, a.g, a.lam0 + i * np, w_old);
                 if (!team_sync(tm)) goto out;
             }
-            // ---------------- v = F(x_old)
+            // ---------------- v = F(x_old), unless the round's batch made it
             tp = wall_clock64();
-            if (!team_fine<DIM, XP, RR, D, IMPL>(tm, a, x_old, v, a.S ? a.S + i * np : nullptr, wk, wk2,
-                                           a.cgb ? a.cgb + (long long)team * a.cgs : nullptr, fine_its))
-                goto out;
+            if constexpr (FBATCH) {
+                if (b[7] && !team_fine_2d_batch<XP, D>(tm, a, i, 1, 1ull, (unsigned long long)(xo & 1)))
+                    goto out;
+            } else {
+                if (!team_fine<DIM, XP, RR, D, IMPL>(tm, a, x_old, v, a.S ? a.S + i * np : nullptr, wk, wk2,
+                                               a.cgb ? a.cgb + (long long)team * a.cgs : nullptr, fine_its))
+                    goto out;
+            }
             {   // uniform code: the phase clocks stay in scalar registers
                 const unsigned long long t = wall_clock64();
                 t_fine += t - tp;
@@ -691,6 +772,7 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                 if (!stale) {
                     L.xo ^= 1;
                     if (!a.incr) L.wo ^= 1;
+                    L.v_valid = 0;   // x_old moved on
                 }
                 L.f_ver = pv;
                 L.f_final = gf;
