@@ -76,12 +76,14 @@ typedef struct pr_config {
     int    cg_maxit;     /* <= 0 means 10*n + 100 */
     double eps;          /* stop when ||lambda^k - lambda^{k-1}||_inf < eps; <= 0: run kmax */
     int    kmax;         /* iteration cap; <= 0 or > N means N (finite termination) */
-    int    tb_depth;     /* fine steps per HBM pass (temporal block depth); 0 = default */
-    int    tile_rows;    /* 2D/3D fine kernel: rows a wave owns; below 96 a register strip
-                            (rows held at once), from 96 on a sliding window (rows marched
-                            per segment, two rows per time level held); 1000: a sliding
-                            window whose segment length is chosen at each launch to fill
-                            the chip's wave slots in whole rounds; 0 = default */
+    int    tb_depth;     /* fine steps per HBM pass (temporal block depth); 0 = default
+                            (2D: 14; 3D: 4 when a slice has more than one step, else 1) */
+    int    tile_rows;    /* 2D/3D fine kernel: rows a wave owns; 2D: below 96 a register
+                            strip (rows held at once), from 96 on a sliding window (rows
+                            marched per segment, two rows per time level held), 1000: a
+                            sliding window whose segment length is chosen at each launch to
+                            fill the chip's wave slots in whole rounds; 3D of depth > 1: the
+                            rows of the lane's column in the z march; 0 = default */
     int    coarse_increment; /* 0: G(new) - G(old) as written in eq. (pr) / Algorithm 2;
                                 1: G applied to the change new - old (G is linear, Section 3.1),
                                 CG from 0 to an absolute residual tol*||new||; an unchanged input

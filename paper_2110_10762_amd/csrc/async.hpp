@@ -282,8 +282,7 @@ __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const do
             fine_its += (unsigned long long)it;
             return true;
         }
-    }
-    if constexpr (DIM == 1) {
+    } else if constexpr (DIM == 1) {
         if (wave_id() == 0) {
             double c[RR], rl[RR];
             load1d<RR>(src, a.n, a.r, c, rl);
@@ -292,34 +291,23 @@ __device__ __forceinline__ bool team_fine(Team &tm, const AsyncArgs &a, const do
         }
         return team_sync(tm);
     } else {
-        const int steps_per = DIM == 2 ? D : 1;
-        const int passes = (a.m + steps_per - 1) / steps_per;
+        // 3D (2D explicit F runs batched per round: team_fine_2d_batch)
+        static_assert(DIM == 3, "2D explicit F is batched");
+        const int passes = a.m;   // one step per pass
         const double *cur = src;
         const int waves = tm.size * nwaves();
         const int wid = tm.rank * nwaves() + wave_id();
         for (int p = 0; p < passes; ++p) {
             double *tgt = ((passes - 1 - p) % 2 == 0) ? dst : scr;
-            if constexpr (DIM == 2) {
-                const int st = min(D, a.m - p * D);
-                const int total = a.nsx * a.nsy;
-                for (int sidx = wid; sidx < total; sidx += waves) {
-                    const int ya = (sidx % a.nsy) * a.rows;   // sliding window over a.rows rows
-                    // two rows in flight: this persistent kernel's occupancy is set by
-                    // its registers, and CG, not F, dominates its time
-                    fine2d_sw<XP, D, 2, false>(cur, tgt, a.n, a.r, st, sidx / a.nsy, ya, min(a.n, ya + a.rows),
-                                               (sidx % a.nsy) & 1);
-                }
-            } else {
-                const int total = a.nsx * a.nsy * a.nsz;
-                for (int sidx = wid; sidx < total; sidx += waves) {
-                    int rem = sidx;
-                    const int sy = rem % a.nsy;
-                    rem /= a.nsy;
-                    const int sz = rem % a.nsz;
-                    const int sx = rem / a.nsz;
-                    const int z0 = sz * a.zc;
-                    fine3d_strip<XP, RR>(cur, tgt, a.n, a.r, sx, sy, z0, min(a.n, z0 + a.zc));
-                }
+            const int total = a.nsx * a.nsy * a.nsz;
+            for (int sidx = wid; sidx < total; sidx += waves) {
+                int rem = sidx;
+                const int sy = rem % a.nsy;
+                rem /= a.nsy;
+                const int sz = rem % a.nsz;
+                const int sx = rem / a.nsz;
+                const int z0 = sz * a.zc;
+                fine3d_strip<XP, RR>(cur, tgt, a.n, a.r, sx, sy, z0, min(a.n, z0 + a.zc));
             }
             if (!team_sync(tm)) return false;
             cur = tgt;
