@@ -251,10 +251,16 @@ __device__ int visible_version(const AsyncArgs &a, int j) {
 __device__ __forceinline__ void team_copy(const Team &tm, const Geom &g, const double *__restrict__ src,
                                           double *__restrict__ dst) {
     const ChunkRange cr = team_chunks(g, tm.rank, tm.size);
-    const int w = wave_id();
-    for (long long c = cr.begin + w; c < cr.end; c += nwaves()) {
-        const Point p = chunk_point(g, c);
-        if (p.valid) dst[p.idx] = src[p.idx];
+    const int nw = nwaves();
+    for (long long c = cr.begin + wave_id(); c < cr.end; c += (long long)STREAM_U * nw) {
+        Point p[STREAM_U];
+        chunk_points<STREAM_U>(g, c, cr.end, nw, p);
+        double t[STREAM_U];
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u) t[u] = src[p[u].idx];
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u)
+            if (p[u].valid) dst[p[u].idx] = t[u];
     }
 }
 
@@ -627,13 +633,23 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
                     // x_new = copy, d = x_new - x_old, ||x_new||^2 (reduced once the copy is valid)
                     nrm_part = 0.0;
                     const ChunkRange cr = team_chunks(a.g, tm.rank, tm.size);
-                    for (long long cc = cr.begin + wave_id(); cc < cr.end; cc += nwaves()) {
-                        const Point p = chunk_point(a.g, cc);
-                        if (!p.valid) continue;
-                        const double xv = src[p.idx];
-                        x_new[p.idx] = xv;
-                        dbuf[p.idx] = xv - x_old[p.idx];
-                        nrm_part = __builtin_fma(xv, xv, nrm_part);
+                    const int nw = nwaves();
+                    for (long long cc = cr.begin + wave_id(); cc < cr.end; cc += (long long)STREAM_U * nw) {
+                        Point p[STREAM_U];
+                        chunk_points<STREAM_U>(a.g, cc, cr.end, nw, p);
+                        double xs[STREAM_U], xp[STREAM_U];
+#pragma unroll
+                        for (int u = 0; u < STREAM_U; ++u) {
+                            xs[u] = src[p[u].idx];
+                            xp[u] = x_old[p[u].idx];
+                        }
+#pragma unroll
+                        for (int u = 0; u < STREAM_U; ++u) {
+                            if (!p[u].valid) continue;
+                            x_new[p[u].idx] = xs[u];
+                            dbuf[p[u].idx] = xs[u] - xp[u];
+                            nrm_part = __builtin_fma(xs[u], xs[u], nrm_part);
+                        }
                     }
                 } else {
                     team_copy(tm, a.g, src, x_new);
@@ -704,14 +720,31 @@ __global__ __launch_bounds__(BLOCK, DIM == 1 ? 1 : 2) void k_async(const AsyncAr
             double dmax = 0.0;
             {
                 const ChunkRange cr = team_chunks(a.g, tm.rank, tm.size);
-                const int w = wave_id();
-                for (long long c = cr.begin + w; c < cr.end; c += nwaves()) {
-                    const Point p = chunk_point(a.g, c);
-                    if (!p.valid) continue;
-                    const double ln = a.incr ? v[p.idx] + (stale ? 0.0 : ybuf[p.idx])
-                                             : v[p.idx] + (wv[p.idx] - w_old[p.idx]);
-                    dmax = fmax(dmax, fabs(ln - cur[p.idx]));
-                    nxt[p.idx] = ln;
+                const int nw = nwaves();
+                // increment form: y = G(change), or 0 when stale; literal form:
+                // w_new and w_old
+                const double *pa = a.incr ? ybuf : wv;
+                const bool use_b = !a.incr;
+                const bool use_a = !(a.incr && stale);
+                for (long long c = cr.begin + wave_id(); c < cr.end; c += (long long)STREAM_U * nw) {
+                    Point p[STREAM_U];
+                    chunk_points<STREAM_U>(a.g, c, cr.end, nw, p);
+                    double tv[STREAM_U], ta[STREAM_U], tb[STREAM_U], tc[STREAM_U];
+#pragma unroll
+                    for (int u = 0; u < STREAM_U; ++u) {
+                        const long long j = p[u].idx;
+                        tv[u] = v[j];
+                        ta[u] = use_a ? pa[j] : 0.0;
+                        tb[u] = use_b ? w_old[j] : 0.0;
+                        tc[u] = cur[j];
+                    }
+#pragma unroll
+                    for (int u = 0; u < STREAM_U; ++u) {
+                        if (!p[u].valid) continue;
+                        const double ln = use_b ? tv[u] + (ta[u] - tb[u]) : tv[u] + ta[u];
+                        dmax = fmax(dmax, fabs(ln - tc[u]));
+                        nxt[p[u].idx] = ln;
+                    }
                 }
             }
             double delta;

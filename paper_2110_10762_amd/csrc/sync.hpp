@@ -189,27 +189,44 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
             its += (unsigned long long)it;
         }
         double nrm = 0.0;
-        for (long long c = cr.begin + w; c < cr.end; c += nw) {
-            const Point p = chunk_point(g, c);
-            if (!p.valid) continue;
-            if (init) {
-                const double wv = B.wn[p.idx];
-                li[p.idx] = wv;
-                wi[p.idx] = wv;
-            } else if (incr) {
-                const double ln = vi[p.idx] + (skip ? 0.0 : B.wn[p.idx]);
-                const double d = ln - li[p.idx];
-                dmax = fmax(dmax, fabs(d));
-                dnext[p.idx] = d;
-                nrm = __builtin_fma(ln, ln, nrm);
-                li[p.idx] = ln;
-            } else {
-                const double wold = wi[p.idx];
-                const double wv = skip ? wold : B.wn[p.idx];
-                const double lnew = vi[p.idx] + (wv - wold);
-                dmax = fmax(dmax, fabs(lnew - li[p.idx]));
-                li[p.idx] = lnew;
-                wi[p.idx] = wv;
+        // the loads of STREAM_U chunks are in flight before any is used; every
+        // lane visits its chunks in the same order as one at a time
+        const bool use_n = !skip;                    // w_new
+        const bool use_v = !init;                    // v and lambda
+        const bool use_w = !init && !incr;           // w_old
+        for (long long c = cr.begin + w; c < cr.end; c += (long long)STREAM_U * nw) {
+            Point p[STREAM_U];
+            chunk_points<STREAM_U>(g, c, cr.end, nw, p);
+            double tn[STREAM_U], tv[STREAM_U], tl[STREAM_U], tw[STREAM_U];
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) {
+                const long long j = p[u].idx;
+                tn[u] = use_n ? B.wn[j] : 0.0;
+                tv[u] = use_v ? vi[j] : 0.0;
+                tl[u] = use_v ? li[j] : 0.0;
+                tw[u] = use_w ? wi[j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) {
+                if (!p[u].valid) continue;
+                const long long j = p[u].idx;
+                if (init) {
+                    li[j] = tn[u];
+                    wi[j] = tn[u];
+                } else if (incr) {
+                    const double ln = tv[u] + tn[u];
+                    const double d = ln - tl[u];
+                    dmax = fmax(dmax, fabs(d));
+                    dnext[j] = d;
+                    nrm = __builtin_fma(ln, ln, nrm);
+                    li[j] = ln;
+                } else {
+                    const double wv = skip ? tw[u] : tn[u];
+                    const double lnew = tv[u] + (wv - tw[u]);
+                    dmax = fmax(dmax, fabs(lnew - tl[u]));
+                    li[j] = lnew;
+                    wi[j] = wv;
+                }
             }
         }
         if (incr) {
