@@ -509,7 +509,13 @@ def main():
     # (read x0 and b, write x, r0, u0) afterwards.
     # Unpreconditioned 2D CG (cg_precond = -1; products recomputed from r and
     # p): iteration 48 (reads r, p_old, x; writes p, x, r'), set-up 24.
-    # Correction 48 (read v, w_new, w_old, lambda_old, write lambda, w).
+    # Correction 48 (read v, w_new, w_old, lambda_old, write lambda, w); in
+    # the initial sweep 24 (read w_new, write lambda, w).  The synchronous
+    # sweep with the preconditioned CG carries each slice's correction in the
+    # set-up march of the next slice's solve: that set-up moves 72 (read x0, v,
+    # w_new, w_old, lambda_old; write x, r0, u0, lambda) and the last slice's
+    # correction of an iteration is a pass of 40 (the same reads, write
+    # lambda).
     D = info.tb_depth
     passes = -(-m // D)
     cg_it_b, cg_set_b, cg_warm_b = (64.0, 32.0, 40.0) if info.cg_precond else (48.0, 24.0, 24.0)
@@ -525,8 +531,12 @@ def main():
                       "launches": f_launches, "avg_launch_ms": f_ms / f_launches,
                       "glups": sum(x["fine_lups"] for x in s) / (f_ms * 1e-3) / 1e9}
         c_ms = sum(x["coarse_ms"] for x in s)
-        c_bytes = sum(x["cg_iters"] * cg_it_b * npts + (N * cg_set_b + (x["g_solves"] - N) * cg_warm_b) * npts
-                      + (x["g_solves"] + x["g_skipped"]) * 48.0 * npts for x in s)
+        if info.cg_precond:   # corrections carried by the set-ups
+            c_bytes = sum((x["cg_iters"] * cg_it_b + N * (cg_set_b + 24.0) + (x["g_solves"] - N) * 72.0
+                           + x["g_skipped"] * 40.0) * npts for x in s)
+        else:
+            c_bytes = sum((x["cg_iters"] * cg_it_b + N * (cg_set_b + 24.0) + (x["g_solves"] - N) * (cg_warm_b + 48.0)
+                           + x["g_skipped"] * 48.0) * npts for x in s)
         c_launches = sum(x["iters"] + 1 for x in s)
         rl["sweep"] = {"kernel": "k_sweep_cg<2,true>" if info.cg_precond else "k_sweep_cg<2,false>", "bound": "hbm", "achieved": c_bytes / (c_ms * 1e-3) / 1e9,
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "launches": c_launches,

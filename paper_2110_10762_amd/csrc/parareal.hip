@@ -122,6 +122,7 @@ struct pr_problem {
     std::vector<Buf> allocs;
     // synchronous workspace (single problem)
     double *v = nullptr, *w = nullptr, *tmp = nullptr, *wn = nullptr, *d0 = nullptr, *d1 = nullptr;
+    double *w2 = nullptr;   // 2D preconditioned sync: coarse values of alternate iterations
     double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *red = nullptr;
     double *cg_r1 = nullptr;   // second residual buffer of the 2D one-synchronisation CG
     double *cg_w0 = nullptr, *cg_w1 = nullptr;   // 2D preconditioned CG: u (p and r shared)
@@ -623,14 +624,24 @@ static int run_sweep(pr_problem *h, const Prob &P, SweepArgs a) {
 }
 
 // ------------------------------------------------------------------ create / destroy
+// Whether the synchronous 2D sweep carries each slice's correction in the
+// set-up march of the next slice's solve: the preconditioned CG in the
+// literal (not incremental) form, with the coarse values of consecutive
+// iterations in alternate buffers.
+static bool carries_corrections(const Prob &P) {
+    return P.dim == 2 && P.pcg && !P.cfg.coarse_increment;
+}
+
 // The iterate-sized buffers of the synchronous driver: fine outputs v, coarse
-// values w and, when a slice takes several fine passes, their ping-pong buffer.
+// values w (and w2, see carries_corrections) and, when a slice takes several
+// fine passes, their ping-pong buffer.
 static int alloc_sync_big(pr_problem *h) {
     const Prob &P = h->P[0];
     const size_t all = (size_t)(P.N + 1) * P.npts;
     int rc;
     if (!h->v && (rc = alloc_t(h, &h->v, all))) return rc;
     if (!h->w && (rc = alloc_t(h, &h->w, all))) return rc;
+    if (carries_corrections(P) && !h->w2 && (rc = alloc_t(h, &h->w2, all))) return rc;
     const int passes = (P.m + fine_depth(P) - 1) / fine_depth(P);
     if (P.dim > 1 && passes > 1 && !h->tmp)
         if ((rc = alloc_t(h, &h->tmp, all))) return rc;
@@ -1105,6 +1116,10 @@ extern "C" int pr_solve_sync(pr_problem *h, const double *u0, double *lam, pr_st
         a.i1 = P.N;
         a.init = 0;
         a.kguard = k;
+        if (carries_corrections(P) && h->w2) {   // w^{k-1} read, w^k written (w^0: the initial sweep's, in w)
+            a.wo = (k & 1) ? h->w : h->w2;
+            a.w = (k & 1) ? h->w2 : h->w;
+        }
         if ((rc = run_sweep(h, P, a))) return rc;
         gs += P.N - k;
         gskip += 1;

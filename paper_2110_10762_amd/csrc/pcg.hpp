@@ -90,9 +90,22 @@ __device__ __forceinline__ Cheb<PD> cheb_coef(double lo, double hi) {
 }
 
 // Raw loads of one march step: input row (r, u, p_old) and output row (x,
-// u, p_old).
+// u, p_old); a set-up that carries the previous slice's correction loads its
+// three terms at both rows (cw, co at the input row, ow, oo at the output
+// row, beside r and uo) and the old lambda at the output row (ol).
 struct PRow {
     double r, u, p, x, uo, po;
+    double cw, co, ow, oo, ol;
+};
+
+// The correction of the previous slice, carried by the set-up march of the
+// next slice's solve: its right-hand side b = v + (wn - wo) (eq. (pr), the
+// terms added in the order of the separate correction pass, so the values
+// are the same bits) is formed at every point the march reads, and stored
+// into lam at the points the wave owns.
+struct SetupCorr {
+    const double *v = nullptr, *wn = nullptr, *wo = nullptr;
+    double *lam = nullptr;
 };
 
 // One iteration of the team's share of the state; accumulates the partial
@@ -100,15 +113,19 @@ struct PRow {
 // SETUP: the start of a solve in the same march, with rin = b, pin = x0 (b,
 // a guess, or null for x0 = 0) and alpha = 1: the first level forms
 // r0 = b - A x0, then u0 = p(A) r0 and w0 = A u0; x = x0 is written and
-// (b, b) summed into bb.
-template <int PD, int PF, bool SETUP, bool SKIP>
+// (b, b) summed into bb.  CORR (with SETUP): when sc is given, b is the
+// previous slice's corrected value formed from sc (rin unused), written to
+// sc->lam at the owned points, and the largest change |b - lam_old| goes
+// into dm.  (sc.v == NULL: no correction; passed by value so that nothing
+// of it lives in memory.)
+template <int PD, int PF, bool SETUP, bool SKIP, bool CORR = false>
 __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int minseg, double s,
                                           const Cheb<PD> &cc, double alpha, double beta, bool first,
                                           const double *__restrict__ rin, const double *__restrict__ uin,
                                           const double *__restrict__ pin, double *__restrict__ rout,
                                           double *__restrict__ uout, double *__restrict__ pout,
                                           double *__restrict__ x, double &ga, double &de, double &rr,
-                                          double &bb) {
+                                          double &bb, const SetupCorr sc = SetupCorr{}, double *dm = nullptr) {
     // Rounding exactly as written (no contraction of the remaining products
     // and sums into fused operations): a point's values come out the same
     // bits in every segment and strip that recomputes them, whatever code
@@ -126,6 +143,12 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
     const int nseg = (n + seg - 1) / seg;
     const int units = nsx * nseg;
     const bool read_p = SETUP ? pin != nullptr : !first;   // p_{-1} = 0; x0 = 0
+    const bool corr = CORR && sc.v != nullptr;
+    const double *__restrict__ cv = sc.v;
+    const double *__restrict__ cwn = sc.wn;
+    const double *__restrict__ cwo = sc.wo;
+    double *__restrict__ clam = sc.lam;
+    double dmax = 0.0;
     for (int un = wid; un < units; un += waves) {
         const int sx = un % nsx;   // strips of the same rows side by side
         const int ya = (un / nsx) * seg;
@@ -154,14 +177,34 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
             double ys;
             const int yi = reflect_row(kk, n, ys);
             const long long rb = (long long)yi * n;
-            w.r = (rin + rb)[xi];
             const int y = min(max(kk - H, ya), yb - 1);
             const long long ob = (long long)y * n;
             if constexpr (SETUP) {   // x0 at both rows, b at the output row
+                // carrying a correction: b's terms at both rows, the old lambda
+                // at the output row (both branches write the same fields in the
+                // same order, so that the slot stays in registers)
+                const double *__restrict__ bsrc = (CORR && corr) ? cv : rin;
+                w.r = (bsrc + rb)[xi];
+                w.uo = (bsrc + ob)[xi];
+                if constexpr (CORR) {
+                    if (corr) {
+                        w.cw = (cwn + rb)[xi];
+                        w.co = (cwo + rb)[xi];
+                        w.ow = (cwn + ob)[xi];
+                        w.oo = (cwo + ob)[xi];
+                        w.ol = (clam + ob)[xi];
+                    } else {
+                        w.cw = 0.0;
+                        w.co = 0.0;
+                        w.ow = 0.0;
+                        w.oo = 0.0;
+                        w.ol = 0.0;
+                    }
+                }
                 w.p = read_p ? (pin + rb)[xi] : 0.0;
                 w.x = read_p ? (pin + ob)[xi] : 0.0;
-                w.uo = (rin + ob)[xi];
             } else {
+                w.r = (rin + rb)[xi];
                 w.u = (uin + rb)[xi];
                 w.p = read_p ? (pin + rb)[xi] : 0.0;
                 w.x = (x + ob)[xi];
@@ -172,7 +215,7 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
         };
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            ring[q] = PRow{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            ring[q] = PRow{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             rsg[q] = 0.0;
             if (q < nrows) issue(k0 + q, ring[q], rsg[q]);
         }
@@ -190,7 +233,8 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
             const double sg = rsg[q];
             // input row k: p_i (set-up: x0) and r_i (set-up: b)
             const double pn = SETUP ? sg * ring[q].p : __builtin_fma(beta, sg * ring[q].p, sg * ring[q].u);
-            const double rk = sg * ring[q].r;
+            // (set-up carrying a correction: b = v + (wn - wo) at row k)
+            const double rk = (CORR && corr) ? sg * (ring[q].r + (ring[q].cw - ring[q].co)) : sg * ring[q].r;
             // s_i = A p_i and r_{i+1} at row k - 1 (set-up: r0 = b - A x0)
             double rn = 0.0;
             if (!SKIP || t >= 2) {
@@ -236,7 +280,13 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
                     const long long i = (long long)y * n + xcol;
                     if constexpr (SETUP) {
                         x[i] = ring[q].x;
-                        bb = __builtin_fma(ring[q].uo, ring[q].uo, bb);
+                        double bo = ring[q].uo;
+                        if (CORR && corr) {
+                            bo = ring[q].uo + (ring[q].ow - ring[q].oo);
+                            dmax = fmax(dmax, fabs(bo - ring[q].ol));
+                            clam[i] = bo;
+                        }
+                        bb = __builtin_fma(bo, bo, bb);
                     } else {
                         const double pi = __builtin_fma(beta, ring[q].po, ring[q].uo);
                         x[i] = __builtin_fma(alpha, pi, ring[q].x);
@@ -261,26 +311,33 @@ __device__ __forceinline__ void cgp_sweep(const Geom &g, int rank, int size, int
             }
         }
     }
+    if (CORR && corr) *dm = fmax(*dm, dmax);
 }
 
 // Solves (I - s h^2 L_h) x = b in 2D by the preconditioned CG above; same
 // start and stop rules as cg_team_dim (abs_thresh2 < 0: x0 = b, or the guess
 // xg when given, relative stop; >= 0: x0 = 0, absolute stop).  Returns the
 // iteration count, or -1 if the launch was aborted.  x must not alias b, xg
-// or the work vectors.
-template <int PD, int MINSEG, int PF = 4, bool SKIP = false>
+// or the work vectors.  CORR: with sc given, b is the previous slice's
+// corrected value formed in the set-up march (b unused; the change goes into
+// *dm; sc.v == NULL: none).
+template <int PD, int MINSEG, int PF = 4, bool SKIP = false, bool CORR = false>
 __device__ int cg_team_2d_p(Team &tm, const Geom &g, double s, double tol, int maxit,
                             const double *__restrict__ b, double *__restrict__ x, const CGWorkP &wk,
-                            double abs_thresh2, const double *__restrict__ xg = nullptr) {
+                            double abs_thresh2, const double *__restrict__ xg = nullptr,
+                            const SetupCorr sc = SetupCorr{}, double *dm = nullptr) {
     const bool from_zero = abs_thresh2 >= 0.0;
     if (from_zero) xg = nullptr;
     // the spectrum of I - s h^2 L_h lies in (1, 1 + 8 s)
     const Cheb<PD> cc = cheb_coef<PD>(1.0, 1.0 + 8.0 * s);
     // the start in one march: x = x0, r0 = b - A x0, u0 = p(A) r0, the sums
     double part[4] = {0.0, 0.0, 0.0, 0.0}, tot[4];
-    cgp_sweep<PD, PF, true, SKIP>(g, tm.rank, tm.size, MINSEG, s, cc, 1.0, 0.0, true, b, nullptr,
-                                  from_zero ? nullptr : (xg ? xg : b), wk.r[0], wk.u[0], nullptr, x, part[0],
-                                  part[1], part[2], part[3]);
+    // a set-up that can carry a correction loads nine values a row pair:
+    // two march steps ahead instead of PF keeps them in registers
+    constexpr int PFS = CORR ? 2 : PF;
+    cgp_sweep<PD, PFS, true, SKIP, CORR>(g, tm.rank, tm.size, MINSEG, s, cc, 1.0, 0.0, true, b, nullptr,
+                                        from_zero ? nullptr : (xg ? xg : b), wk.r[0], wk.u[0], nullptr, x,
+                                        part[0], part[1], part[2], part[3], sc, dm);
     if (!team_reduce_n<4>(tm, part, wk.red, tot)) return -1;
     double gamma = tot[0], rho = tot[2];
     const double thresh = from_zero ? (abs_thresh2 > 0.0 ? abs_thresh2 : tol * tol * tot[3]) : tol * tol * tot[3];

@@ -24,6 +24,9 @@ struct SweepArgs {
     const double *v;    // [(N+1) * npts], v[i] = F(lambda_{i-1})
     double *w;          // [(N+1) * npts], w[i] = G of slice i's last coarse input
     double *wn;         // [npts] scratch for the new coarse value
+    const double *wo;   // 2D preconditioned, not incremental: [(N+1) * npts], the
+                        // previous iteration's coarse values (then w receives the
+                        // new ones directly); NULL: w is updated in place
     long long npts;
     int i0, i1;         // slices to sweep, inclusive
     int kguard;         // slice whose coarse input is known unchanged (-1: none)
@@ -115,12 +118,14 @@ struct SweepBufs {
     double *lam;
     const double *v;
     double *w, *wn, *d0, *d1;
+    const double *wo = nullptr;   // previous coarse values, when the corrections ride on the set-ups
 };
 
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWork &wk, double abs_thresh2,
-                                       const double *xg = nullptr) {
+                                       const double *xg = nullptr, const SetupCorr = SetupCorr{},
+                                       double * = nullptr) {
     // 3D whole-GPU sweep: marching phases (7.7 s for the 3D workload against
     // 8.7 s with two chunks per wave in flight and 9.0 s with one; the
     // one-synchronisation form with w and s stored moves 80 B per point and
@@ -131,7 +136,8 @@ __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWork2 &wk, double abs_thresh2,
-                                       const double * = nullptr) {   // starts from b
+                                       const double * = nullptr, const SetupCorr = SetupCorr{},
+                                       double * = nullptr) {   // starts from b
     static_assert(DIM == 2, "the recomputing CG is two-dimensional");
     // the whole GPU has more waves than a state has rows per column strip:
     // every wave takes a few chunks (the marching sweep measured 1.6x slower)
@@ -141,7 +147,8 @@ __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWork2M &wk, double abs_thresh2,
-                                       const double * = nullptr) {   // starts from b
+                                       const double * = nullptr, const SetupCorr = SetupCorr{},
+                                       double * = nullptr) {   // starts from b
     static_assert(DIM == 2, "the recomputing CG is two-dimensional");
     return cg_team_2d_r<true>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2);
 }
@@ -149,15 +156,18 @@ __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWorkP &wk, double abs_thresh2,
-                                       const double *xg = nullptr) {
+                                       const double *xg = nullptr, const SetupCorr sc = SetupCorr{},
+                                       double *dm = nullptr) {
     static_assert(DIM == 2, "the preconditioned CG is two-dimensional");
-    return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_GPU, 4, true>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2, xg);
+    return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_GPU, 4, true, true>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2, xg,
+                                                                   sc, dm);
 }
 
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWorkPT &wk, double abs_thresh2,
-                                       const double *xg = nullptr) {
+                                       const double *xg = nullptr, const SetupCorr = SetupCorr{},
+                                       double * = nullptr) {
     static_assert(DIM == 2, "the preconditioned CG is two-dimensional");
     return cg_team_2d_p<PCG_DEGREE, PCG_MINSEG_TEAM, 2>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2, xg);
 }
@@ -170,6 +180,14 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
     const int w = wave_id();
     const int nw = nwaves();
     incr = incr && !init;
+    // Corrections carried by the set-ups (B.wo given; literal form): slice i's
+    // solve reads x0 from B.wo and writes G(lambda_{i-1}) into B.w directly,
+    // and its set-up march forms the previous slice's correction where it
+    // reads its input, so no pass and no barrier separate the solves; the
+    // last slice's correction is a pass after the loop.
+    const bool carry = B.wo != nullptr && !init && !incr;
+    int pend = -1;            // slice whose correction is still to be made
+    bool pend_skip = false;   // ... with its coarse solve skipped
     double *dprev = B.d0, *dnext = B.d1;
     double nrm_prev = 0.0;
     for (int i = i0; i <= i1; ++i) {
@@ -178,15 +196,27 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
         double *wi = B.w + (long long)i * npts;
         const double *vi = B.v + (long long)i * npts;
         if (!skip) {
+            SetupCorr sc{};
+            if (carry && pend == i - 1) {
+                const double *wo_p = B.wo + (long long)(i - 1) * npts;
+                sc = SetupCorr{B.v + (long long)(i - 1) * npts, pend_skip ? wo_p : B.w + (long long)(i - 1) * npts,
+                               wo_p, B.lam + (long long)(i - 1) * npts};
+            }
             // one call site: the kernel holds a single copy of the solver.  A
             // solve of the literal form starts from the slice's last coarse
             // value G(lambda_{i-1}^{k-1}): its residual is then the change of
             // the input, small once the iteration settles (same stop rule)
             const int it = team_cg<DIM>(tm, g, s, tol, maxit, incr ? dprev : B.lam + (long long)(i - 1) * npts,
-                                        B.wn, wk, incr ? tol * tol * nrm_prev : -1.0,
-                                        (init || incr) ? nullptr : wi);
+                                        carry ? wi : B.wn, wk, incr ? tol * tol * nrm_prev : -1.0,
+                                        (init || incr) ? nullptr : (carry ? B.wo + (long long)i * npts : wi), sc,
+                                        &dmax);
             if (it < 0) return false;
             its += (unsigned long long)it;
+        }
+        if (carry) {
+            pend = i;
+            pend_skip = skip;
+            continue;
         }
         double nrm = 0.0;
         // the loads of STREAM_U chunks are in flight before any is used; every
@@ -238,6 +268,32 @@ __device__ bool team_coarse_sweep(Team &tm, const Geom &g, double s, double tol,
             return false;
         }
     }
+    if (carry && pend >= 0) {   // the last slice's correction (the launch ends after it)
+        double *li = B.lam + (long long)pend * npts;
+        const double *vi = B.v + (long long)pend * npts;
+        const double *wo_p = B.wo + (long long)pend * npts;
+        const double *wn_p = pend_skip ? wo_p : B.w + (long long)pend * npts;
+        for (long long c = cr.begin + w; c < cr.end; c += (long long)STREAM_U * nw) {
+            Point p[STREAM_U];
+            chunk_points<STREAM_U>(g, c, cr.end, nw, p);
+            double tv[STREAM_U], tn[STREAM_U], to[STREAM_U], tl[STREAM_U];
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) {
+                const long long j = p[u].idx;
+                tv[u] = vi[j];
+                tn[u] = wn_p[j];
+                to[u] = wo_p[j];
+                tl[u] = li[j];
+            }
+#pragma unroll
+            for (int u = 0; u < STREAM_U; ++u) {
+                if (!p[u].valid) continue;
+                const double lnew = tv[u] + (tn[u] - to[u]);
+                dmax = fmax(dmax, fabs(lnew - tl[u]));
+                li[p[u].idx] = lnew;
+            }
+        }
+    }
     return true;
 }
 
@@ -260,7 +316,7 @@ __global__ __launch_bounds__(sweep_threads(PCG)) void k_sweep_cg(SweepArgs a) {
     __shared__ double lds[MAX_WAVES];
     double dmax = 0.0;
     unsigned long long its = 0;
-    const SweepBufs B{a.lam, a.v, a.w, a.wn, a.d0, a.d1};
+    const SweepBufs B{a.lam, a.v, a.w, a.wn, a.d0, a.d1, (DIM == 2 && PCG) ? a.wo : nullptr};
     bool ok;
     if constexpr (DIM == 2 && PCG)
         ok = team_coarse_sweep<2>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
