@@ -549,8 +549,9 @@ def main():
         for x in a:
             upd = x["kernel_updates"]
             solves = x["g_solves"] - N          # minus the initial coarse sweep
-            # per update: F passes, predecessor copy 16, correction + next slot 48
-            a_bytes += (upd * (a_passes * 16.0 + 16.0 + 48.0) + x["kernel_cg_iters"] * cg_it_b
+            # per update: F passes, predecessor copy 16, correction + next slot
+            # 40 (read v, w_new, w_old and the current slot; write the next)
+            a_bytes += (upd * (a_passes * 16.0 + 16.0 + 40.0) + x["kernel_cg_iters"] * cg_it_b
                         + solves * cg_warm_b) * npts
         rl["async"] = {"kernel": f"k_async<2,2,0,{ASYNC_DEPTH},false,{'true' if info.cg_precond else 'false'}>",
                        "bound": "hbm",
