@@ -252,9 +252,13 @@ def run_extras(dev):
              "rel_err_vs_gpu_serial_fine": (got - ser).abs().max().item() / sref}
         if drv == "sync":
             r["fine_ms"], r["coarse_ms"] = st.fine_ms, st.coarse_ms
-            # set-up 24 B from x0 = b (initial sweep), 32 from the last coarse value
-            c_bytes = (st.cg_iters * 64.0 + N * 24.0 + (st.g_solves - N) * 32.0
-                       + (st.g_solves + st.g_skipped) * 48.0) * npts
+            # set-up 24 B from x0 = b (initial sweep, then 24 to store lambda^0
+            # and w^0); afterwards each set-up carries the previous slice's
+            # correction: 64 (read x0, v, w_new, w_old, lambda_old; write x, r,
+            # lambda), and the last slice of an iteration corrects in a pass of
+            # 40 (the same reads, write lambda)
+            c_bytes = (st.cg_iters * 64.0 + N * (24.0 + 24.0) + (st.g_solves - N) * 64.0
+                       + st.g_skipped * 40.0) * npts
             r["roofline_sweep"] = {"kernel": "k_sweep_cg<3>", "bound": "hbm",
                                    "achieved": c_bytes / (st.coarse_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": c_bytes / (st.coarse_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}

@@ -314,20 +314,35 @@ __device__ __forceinline__ double cpt_apply(const CPt &q, const double (&v)[2 * 
 //   CG3_B: v = p; x += alpha v, r -= alpha A v (in place), sum r.r;
 //   CG3_S: v = b (set-up with x0 = b); x = b, r = b - A b, sums r.r and b.b;
 //   CG3_W: v = x0, a given guess (set-up); x = x0, r = b - A x0 with b (vb)
-//          read at the output point, sums r.r and b.b.
+//          read at the output point, sums r.r and b.b;
+//   CG3_WC: CG3_W carrying the previous slice's correction: b = v + (wn - wo)
+//          from the terms at the output point (vb = the correction's v), also
+//          stored into lam, with the largest change |b - lam_old|.
 // A v is formed exactly as in the chunk-wise phases (cpt_apply's order).
-enum { CG3_A = 0, CG3_B = 1, CG3_S = 2, CG3_W = 3 };
+enum { CG3_A = 0, CG3_B = 1, CG3_S = 2, CG3_W = 3, CG3_WC = 4 };
+
+// The correction of the previous slice, carried by the set-up march of the
+// next slice's solve: its right-hand side b = v + (wn - wo) (eq. (pr), the
+// terms added in the order of the separate correction pass, so the values
+// are the same bits) is formed where the march reads b, and stored into lam
+// at the points the wave owns.  v == NULL: no correction.
+struct SetupCorr {
+    const double *v = nullptr, *wn = nullptr, *wo = nullptr;
+    double *lam = nullptr;
+};
 
 struct SW3Row {    // raw loads for one step: centre row (with the strip-border
-                   // point) and the two side rows, of one or two vectors
+                   // point) and the two side rows, of one or two vectors;
+                   // CG3_WC: the correction's terms at the output point
     double ac, ae, am, ap, bc, be, bm, bp, xo, ro;
+    double cw, co, cl;
 };
 
 template <int MODE>
 __device__ __forceinline__ void sw3_issue(const double *__restrict__ va, const double *__restrict__ vb,
                                           const double *__restrict__ x, const double *__restrict__ r, int n, int z,
                                           int k, int ya, int yb, int xcol, bool lv, int eoff, bool eok,
-                                          bool use_b, SW3Row &w) {
+                                          bool use_b, SW3Row &w, const SetupCorr &sc) {
     const long long plane = (long long)n * n;
     const bool kok = k >= 0 && k < n;
     const int y = k - 1;                        // output row of this step
@@ -354,6 +369,13 @@ __device__ __forceinline__ void sw3_issue(const double *__restrict__ va, const d
         w.ro = r[io];
     }
     if constexpr (MODE == CG3_W) w.ro = vb[(yok && lv) ? ob : 0];   // b at the output point
+    if constexpr (MODE == CG3_WC) {   // b's terms and the old lambda at the output point
+        const long long io = (yok && lv) ? ob : 0;
+        w.ro = vb[io];
+        w.cw = sc.wn[io];
+        w.co = sc.wo[io];
+        w.cl = sc.lam[io];
+    }
 }
 
 template <int MODE, int PF>
@@ -361,8 +383,10 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
                                              bool first, const double *__restrict__ va,
                                              const double *__restrict__ vb, double *__restrict__ x,
                                              double *__restrict__ r, double *__restrict__ pout, double &acc0,
-                                             double &acc1) {
+                                             double &acc1, const SetupCorr sc = SetupCorr{},
+                                             double *dm = nullptr) {
     const int n = g.n;
+    double dml = 0.0;   // CG3_WC: largest change of the carried correction
     const int lane = threadIdx.x & (WAVE - 1);
     const bool l0 = lane == 0, l63 = lane == WAVE - 1;
     const int waves = size * nwaves();
@@ -389,7 +413,7 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
 #pragma unroll
         for (int q = 0; q < PF; ++q)
             if (q < nrows)
-                sw3_issue<MODE>(va, vb, x, r, n, z, ya - 1 + q, ya, yb, xcol, lv, eoff, eok, use_b, ring[q]);
+                sw3_issue<MODE>(va, vb, x, r, n, z, ya - 1 + q, ya, yb, xcol, lv, eoff, eok, use_b, ring[q], sc);
         for (int tb = 0; tb < nrows; tb += PF) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
@@ -398,7 +422,7 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
                 const int k = ya - 1 + t;
                 const SW3Row w = ring[q];
                 if (t + PF < nrows)
-                    sw3_issue<MODE>(va, vb, x, r, n, z, k + PF, ya, yb, xcol, lv, eoff, eok, use_b, ring[q]);
+                    sw3_issue<MODE>(va, vb, x, r, n, z, k + PF, ya, yb, xcol, lv, eoff, eok, use_b, ring[q], sc);
                 const bool kok = k >= 0 && k < n;
                 const int y = k - 1;
                 const bool yok = y >= ya && y < yb;
@@ -437,6 +461,15 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
                             r[i] = rv;
                             acc0 = __builtin_fma(rv, rv, acc0);
                             acc1 = __builtin_fma(vm1c, vm1c, acc1);
+                        } else if constexpr (MODE == CG3_WC) {
+                            const double bo = w.ro + (w.cw - w.co);
+                            dml = fmax(dml, fabs(bo - w.cl));
+                            sc.lam[i] = bo;
+                            const double rv = bo - av;
+                            x[i] = vm1c;
+                            r[i] = rv;
+                            acc0 = __builtin_fma(rv, rv, acc0);
+                            acc1 = __builtin_fma(bo, bo, acc1);
                         } else {
                             const double rv = w.ro - av;
                             x[i] = vm1c;
@@ -453,6 +486,7 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
             }
         }
     }
+    if constexpr (MODE == CG3_WC) *dm = fmax(*dm, dml);
 }
 
 // Solves (I - s h^2 L_h) x = b by CG with the team (DIM = 2 or 3; U chunks
@@ -472,10 +506,13 @@ __device__ __forceinline__ void cg3_sweep_sw(const Geom &g, int rank, int size, 
 // A's value) instead of storing it: 64 B of HBM traffic per point.
 // SW3 (DIM = 3): the two phases and the set-up from x0 = b march
 // (cg3_sweep_sw) instead of visiting chunks.
+// SW3 with a guess xg and sc.v given: the set-up carries the previous slice's
+// correction (CG3_WC; b unused, the change goes into *dm).
 template <int DIM, int U, bool SW3 = false>
 __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int maxit,
                            const double *__restrict__ b, double *__restrict__ x, const CGWork &wk,
-                           double abs_thresh2, const double *__restrict__ xg = nullptr) {
+                           double abs_thresh2, const double *__restrict__ xg = nullptr,
+                           const SetupCorr sc = SetupCorr{}, double *dm = nullptr) {
     static_assert(!SW3 || DIM == 3, "the marching phases are three-dimensional");
     constexpr int V = 2 * DIM;
     __shared__ double lds[MAX_WAVES];
@@ -488,7 +525,9 @@ __device__ int cg_team_dim(Team &tm, const Geom &g, double s, double tol, int ma
     const bool from_zero = abs_thresh2 >= 0.0;
 
     double rr_p = 0.0, bb_p = 0.0, unused = 0.0;
-    if (SW3 && !from_zero && xg)
+    if (SW3 && !from_zero && xg && sc.v)
+        cg3_sweep_sw<CG3_WC, 4>(g, tm.rank, tm.size, s, 0.0, true, xg, sc.v, x, r, nullptr, rr_p, bb_p, sc, dm);
+    else if (SW3 && !from_zero && xg)
         cg3_sweep_sw<CG3_W, 4>(g, tm.rank, tm.size, s, 0.0, true, xg, b, x, r, nullptr, rr_p, bb_p);
     else if (SW3 && !from_zero)
         cg3_sweep_sw<CG3_S, 4>(g, tm.rank, tm.size, s, 0.0, true, b, nullptr, x, r, nullptr, rr_p, bb_p);

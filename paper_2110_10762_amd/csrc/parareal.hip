@@ -624,12 +624,12 @@ static int run_sweep(pr_problem *h, const Prob &P, SweepArgs a) {
 }
 
 // ------------------------------------------------------------------ create / destroy
-// Whether the synchronous 2D sweep carries each slice's correction in the
-// set-up march of the next slice's solve: the preconditioned CG in the
-// literal (not incremental) form, with the coarse values of consecutive
-// iterations in alternate buffers.
+// Whether the synchronous sweep carries each slice's correction in the
+// set-up march of the next slice's solve: the marching solvers (2D
+// preconditioned CG, 3D CG) in the literal (not incremental) form, with the
+// coarse values of consecutive iterations in alternate buffers.
 static bool carries_corrections(const Prob &P) {
-    return P.dim == 2 && P.pcg && !P.cfg.coarse_increment;
+    return (P.dim == 3 || (P.dim == 2 && P.pcg)) && !P.cfg.coarse_increment;
 }
 
 // The iterate-sized buffers of the synchronous driver: fine outputs v, coarse

@@ -98,15 +98,6 @@ struct PRow {
     double cw, co, ow, oo, ol;
 };
 
-// The correction of the previous slice, carried by the set-up march of the
-// next slice's solve: its right-hand side b = v + (wn - wo) (eq. (pr), the
-// terms added in the order of the separate correction pass, so the values
-// are the same bits) is formed at every point the march reads, and stored
-// into lam at the points the wave owns.
-struct SetupCorr {
-    const double *v = nullptr, *wn = nullptr, *wo = nullptr;
-    double *lam = nullptr;
-};
 
 // One iteration of the team's share of the state; accumulates the partial
 // sums of (r', u'), (w', u') and (r', r') over the points the wave owns.

@@ -24,7 +24,7 @@ struct SweepArgs {
     const double *v;    // [(N+1) * npts], v[i] = F(lambda_{i-1})
     double *w;          // [(N+1) * npts], w[i] = G of slice i's last coarse input
     double *wn;         // [npts] scratch for the new coarse value
-    const double *wo;   // 2D preconditioned, not incremental: [(N+1) * npts], the
+    const double *wo;   // marching solvers (2D preconditioned, 3D), not incremental: [(N+1) * npts], the
                         // previous iteration's coarse values (then w receives the
                         // new ones directly); NULL: w is updated in place
     long long npts;
@@ -124,13 +124,13 @@ struct SweepBufs {
 template <int DIM>
 __device__ __forceinline__ int team_cg(Team &tm, const Geom &g, double s, double tol, int maxit,
                                        const double *b, double *x, const CGWork &wk, double abs_thresh2,
-                                       const double *xg = nullptr, const SetupCorr = SetupCorr{},
-                                       double * = nullptr) {
+                                       const double *xg = nullptr, const SetupCorr sc = SetupCorr{},
+                                       double *dm = nullptr) {
     // 3D whole-GPU sweep: marching phases (7.7 s for the 3D workload against
     // 8.7 s with two chunks per wave in flight and 9.0 s with one; the
     // one-synchronisation form with w and s stored moves 80 B per point and
     // took 10.9 s)
-    return cg_team_dim<DIM, 2, DIM == 3>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2, xg);
+    return cg_team_dim<DIM, 2, DIM == 3>(tm, g, s, tol, maxit, b, x, wk, abs_thresh2, xg, sc, dm);
 }
 
 template <int DIM>
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(sweep_threads(PCG)) void k_sweep_cg(SweepArgs a) {
     __shared__ double lds[MAX_WAVES];
     double dmax = 0.0;
     unsigned long long its = 0;
-    const SweepBufs B{a.lam, a.v, a.w, a.wn, a.d0, a.d1, (DIM == 2 && PCG) ? a.wo : nullptr};
+    const SweepBufs B{a.lam, a.v, a.w, a.wn, a.d0, a.d1, (DIM == 3 || PCG) ? a.wo : nullptr};
     bool ok;
     if constexpr (DIM == 2 && PCG)
         ok = team_coarse_sweep<2>(tm, a.g, a.s, a.cg_tol, a.cg_maxit, a.npts, a.i0, a.i1, a.kguard, a.init != 0,
