@@ -40,10 +40,10 @@ ASYNC_DEPTH = 12        # fine steps per pass inside the persistent asynchronous
 # plain copy of known size gives), kept in profiles/.  They describe the
 # kernel sources whose code (comments aside) has this digest and are reported
 # as null once that code changes.
-PROFILED_SOURCES = "6f5a0c5e9b718d57"
-PROFILED_TRAFFIC = {"async": 388.62 + 254.38,      # GB, one launch
-                    "fine": 0.4958 + 0.4745,       # GB, mean over the sync solve's passes
-                    "sweep": 17.288 + 11.129}      # GB, mean over the sync solve's sweeps
+PROFILED_SOURCES = "d4747fc9cb7c5f11"
+PROFILED_TRAFFIC = {"async": 386.86 + 259.08,      # GB, one launch
+                    "fine": 0.4956 + 0.4745,       # GB, mean over the sync solve's passes
+                    "sweep": 17.334 + 11.129}      # GB, mean over the sync solve's sweeps
 
 
 def sources_digest():
