@@ -641,7 +641,8 @@ static int alloc_sync_big(pr_problem *h) {
     int rc;
     if (!h->v && (rc = alloc_t(h, &h->v, all))) return rc;
     if (!h->w && (rc = alloc_t(h, &h->w, all))) return rc;
-    if (carries_corrections(P) && !h->w2 && (rc = alloc_t(h, &h->w2, all))) return rc;
+    // optional: without it each slice is corrected in a pass of its own
+    if (carries_corrections(P) && !h->w2 && alloc_t(h, &h->w2, all) != PR_OK) h->w2 = nullptr;
     const int passes = (P.m + fine_depth(P) - 1) / fine_depth(P);
     if (P.dim > 1 && passes > 1 && !h->tmp)
         if ((rc = alloc_t(h, &h->tmp, all))) return rc;
