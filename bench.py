@@ -40,10 +40,10 @@ ASYNC_DEPTH = 12        # fine steps per pass inside the persistent asynchronous
 # plain copy of known size gives), kept in profiles/.  They describe the
 # kernel sources whose code (comments aside) has this digest and are reported
 # as null once that code changes.
-PROFILED_SOURCES = "d4747fc9cb7c5f11"
-PROFILED_TRAFFIC = {"async": 386.86 + 259.08,      # GB, one launch
-                    "fine": 0.4956 + 0.4745,       # GB, mean over the sync solve's passes
-                    "sweep": 17.334 + 11.129}      # GB, mean over the sync solve's sweeps
+PROFILED_SOURCES = "2a4660fdd90cacf5"
+PROFILED_TRAFFIC = {"async": 390.40 + 258.26,      # GB, one launch
+                    "fine": 0.4954 + 0.4745,       # GB, mean over the sync solve's passes
+                    "sweep": 17.191 + 11.129}      # GB, mean over the sync solve's sweeps
 
 
 def sources_digest():
